@@ -1,0 +1,219 @@
+"""CPU oracle for the sparse-Cholesky path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct FP64 reference, written from the paper
+(Schaefer, Sullivan, Owhadi, arXiv:1706.02205).  Only the test-suite, the
+package smoke check and the benchmark's CPU-baseline leg may import this
+module; the product library never calls it and shares no code with it.
+
+The heavy loops live in ``kchol_oracle.c`` (gcc, -ffp-contract=off); this
+file marshals numpy arrays through ctypes and adds the small dense helpers.
+Functions and the passages they follow:
+
+* :func:`maximin`       greedy maximin ordering, O(N^2)           -- Section 2.3
+* :func:`pattern`       sparsity pattern S_rho (max or min rule)   -- Section 2.3 / Section 6.2
+* :func:`theta_on_pattern`  Matern covariance on S                 -- Section 4.4 (Matern definition)
+* :func:`ichol`         right-looking ICHOL(0)                     -- Section 2.2 (incomplete Cholesky)
+* :func:`solve`         x = P^T L^-T L^-1 P b                      -- Section 1, task (2)
+* :func:`llt_pairs`, :func:`mc_error`, :func:`frob_error`  error E -- Section 4.4
+
+Parity status: every function above is pinned by ``tests/test_oracle_*.py``
+(closed forms, library special cases, brute force on tiny inputs, and the
+paper's printed nnz and error statistics).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+RULE_MAX, RULE_MIN = 0, 1
+PIVOT_ZERO, PIVOT_SHIFT = 0, 1
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        I64, I32, F64 = C.c_int64, C.c_int32, C.c_double
+        L.or_maximin.argtypes = [_f64p, I64, I32, _i32p, _f64p]
+        L.or_pattern_count.argtypes = [_f64p, I64, I32, _f64p, F64, I32, _i64p]
+        L.or_pattern_fill.argtypes = [_f64p, I64, I32, _f64p, F64, I32, _i64p, _i32p]
+        L.or_matern.argtypes = [_f64p, I64, F64, F64, _f64p]
+        L.or_theta.argtypes = [_f64p, I64, I32, F64, F64, _i64p, _i32p, _f64p]
+        L.or_ichol.argtypes = [I64, _i64p, _i32p, _f64p, I32, F64, _f64p, _i64p]
+        L.or_solve.argtypes = [I64, _i64p, _i32p, _f64p, I32, _f64p, _f64p]
+        L.or_llt_pairs.argtypes = [I64, _i64p, _i32p, _f64p, I64, _i64p, _i64p, _f64p]
+        L.or_frob_error.argtypes = [_f64p, I64, I32, F64, F64, _i64p, _i32p, _f64p, _f64p]
+        L.or_num_threads.argtypes = []
+        for fn in ("or_maximin", "or_pattern_count", "or_pattern_fill", "or_matern", "or_theta", "or_ichol",
+                   "or_solve", "or_llt_pairs", "or_frob_error", "or_num_threads"):
+            getattr(L, fn).restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+# --------------------------------------------------------------------------
+@dataclass
+class Pattern:
+    perm: np.ndarray     # int32[n]: maximin position -> original index
+    l: np.ndarray        # float64[n]: l[k] = distance of the k-th point to the earlier ones
+    colptr: np.ndarray   # int64[n+1]
+    rowidx: np.ndarray   # int32[nnz], ascending within each column, diagonal first
+    xh: np.ndarray       # (n, d) points gathered into maximin order
+
+    @property
+    def n(self) -> int:
+        return int(self.perm.shape[0])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colptr[-1])
+
+
+def maximin(x: np.ndarray):
+    """Greedy maximin ordering (Section 2.3), brute force O(N^2).
+
+    Returns (perm, l): perm[k] is the original index of the k-th point and
+    l[k] its distance to the points before it (l[0] = +inf).  First index:
+    original index 0; ties: lowest original index."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n, d = x.shape
+    perm = np.empty(n, np.int32)
+    l = np.empty(n, np.float64)
+    _check(lib().or_maximin(x, n, d, perm, l), "maximin")
+    return perm, l
+
+
+def pattern(x: np.ndarray, rho: float, rule: int = RULE_MAX, ordering=None) -> Pattern:
+    """Pattern S_rho (Section 2.3) on the maximin ordering, brute force O(N^2).
+
+    Lower triangle in CSC over maximin positions, diagonal included."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n, d = x.shape
+    perm, l = ordering if ordering is not None else maximin(x)
+    xh = np.ascontiguousarray(x[perm])
+    colptr = np.empty(n + 1, np.int64)
+    _check(lib().or_pattern_count(xh, n, d, l, float(rho), int(rule), colptr), "pattern_count")
+    rowidx = np.empty(int(colptr[-1]), np.int32)
+    _check(lib().or_pattern_fill(xh, n, d, l, float(rho), int(rule), colptr, rowidx), "pattern_fill")
+    return Pattern(perm, l, colptr, rowidx, xh)
+
+
+def matern(r: np.ndarray, nu: float, ell: float) -> np.ndarray:
+    """Matern covariance at distances r (Section 4.4), nu in {1/2, 3/2, 5/2}."""
+    r = np.ascontiguousarray(r, dtype=np.float64).ravel()
+    out = np.empty_like(r)
+    _check(lib().or_matern(r, r.size, float(nu), float(ell), out), "matern")
+    return out
+
+
+def theta_on_pattern(P: Pattern, nu: float, ell: float) -> np.ndarray:
+    """Theta_ab = G(x_a, x_b) for every (a,b) in S, in CSC order."""
+    out = np.empty(P.nnz, np.float64)
+    n, d = P.xh.shape
+    _check(lib().or_theta(P.xh, n, d, float(nu), float(ell), P.colptr, P.rowidx, out), "theta")
+    return out
+
+
+@dataclass
+class IcholResult:
+    L: np.ndarray          # CSC values aligned with the pattern's rowidx
+    nonpositive: int
+    shifted: int
+    updates: int
+
+    @property
+    def rank(self) -> int:
+        return -1  # filled by callers that know n
+
+
+def ichol(P: Pattern, theta: np.ndarray, policy: int = PIVOT_ZERO, tau: float = 0.0) -> IcholResult:
+    """ICHOL(0) (Section 2.2) in the paper's right-looking order."""
+    L = np.empty(P.nnz, np.float64)
+    stats = np.zeros(3, np.int64)
+    _check(lib().or_ichol(P.n, P.colptr, P.rowidx, np.ascontiguousarray(theta, dtype=np.float64), int(policy),
+                          float(tau), L, stats), "ichol")
+    return IcholResult(L, int(stats[0]), int(stats[1]), int(stats[2]))
+
+
+def solve_permuted(P: Pattern, L: np.ndarray, bh: np.ndarray) -> np.ndarray:
+    """L^-T L^-1 bh for bh (n, nrhs) already in maximin order."""
+    bh = np.ascontiguousarray(bh, dtype=np.float64)
+    if bh.ndim == 1:
+        bh = bh[:, None]
+    out = np.empty_like(bh)
+    _check(lib().or_solve(P.n, P.colptr, P.rowidx, np.ascontiguousarray(L), bh.shape[1], bh, out), "solve")
+    return out
+
+
+def solve(P: Pattern, L: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """x = P^T L^-T L^-1 P b in the caller's original point order."""
+    b2 = b[:, None] if b.ndim == 1 else b
+    xh = solve_permuted(P, L, b2[P.perm])
+    x = np.empty_like(xh)
+    x[P.perm] = xh
+    return x[:, 0] if b.ndim == 1 else x
+
+
+def llt_pairs(P: Pattern, L: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """(L L^T)_{a,b} for arrays of maximin positions."""
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    b = np.ascontiguousarray(b, dtype=np.int64)
+    out = np.empty(a.size, np.float64)
+    _check(lib().or_llt_pairs(P.n, P.colptr, P.rowidx, np.ascontiguousarray(L), a.size, a, b, out), "llt_pairs")
+    return out
+
+
+def mc_error(P: Pattern, L: np.ndarray, nu: float, ell: float, pairs: np.ndarray, box=None) -> float:
+    """Sampled relative Frobenius error E of Section 4.4 over index pairs.
+
+    ``pairs`` are maximin positions; with ``box=(lo, hi)`` only pairs whose two
+    points lie in [lo, hi]^d are kept (the paper's E-bar)."""
+    a, b = pairs[:, 0], pairs[:, 1]
+    if box is not None:
+        lo, hi = box
+        keep = np.all((P.xh[a] >= lo) & (P.xh[a] <= hi), axis=1) & np.all((P.xh[b] >= lo) & (P.xh[b] <= hi), axis=1)
+        a, b = a[keep], b[keep]
+    th = matern(np.sqrt(((P.xh[a] - P.xh[b]) ** 2).sum(axis=1)), nu, ell)
+    approx = llt_pairs(P, L, a, b)
+    return float(np.sqrt(((approx - th) ** 2).sum()) / np.sqrt((th ** 2).sum()))
+
+
+def frob_error(P: Pattern, L: np.ndarray, nu: float, ell: float) -> float:
+    """Exact ||L L^T - Theta||_F / ||Theta||_F over all N^2 pairs."""
+    out = np.empty(2, np.float64)
+    n, d = P.xh.shape
+    _check(lib().or_frob_error(P.xh, n, d, float(nu), float(ell), P.colptr, P.rowidx, np.ascontiguousarray(L), out),
+           "frob_error")
+    return float(np.sqrt(out[0] / out[1]))
+
+
+def dense_from_csc(P: Pattern, vals: np.ndarray) -> np.ndarray:
+    """Dense lower-triangular matrix from CSC values (small n only)."""
+    n = P.n
+    M = np.zeros((n, n))
+    cols = np.repeat(np.arange(n), np.diff(P.colptr))
+    M[P.rowidx, cols] = vals
+    return M
