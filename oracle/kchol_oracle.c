@@ -194,7 +194,8 @@ int or_theta(const double *xh, int64_t n, int32_t d, double nu, double ell, cons
  * Pivot rule (Section 4.4): a nonpositive pivot zeroes the column, which then
  * contributes no updates (ZERO).  SHIFT instead raises a pivot p <= tau*Theta_ii
  * to tau*Theta_ii and counts it.
- * stats[0] = #nonpositive (zeroed), stats[1] = #shifted, stats[2] = #updates. */
+ * stats[0] = #nonpositive (zeroed), stats[1] = #shifted, stats[2] = #updates with a
+ * nonzero multiplier L_ji (a zeroed column performs none). */
 int or_ichol(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *theta, int32_t policy,
              double tau, double *L, int64_t *stats) {
     if (n < 1 || (policy != OR_PIVOT_ZERO && policy != OR_PIVOT_SHIFT)) return OR_EINVAL;
@@ -230,7 +231,7 @@ int or_ichol(int64_t n, const int64_t *colptr, const int32_t *rowidx, const doub
                 int64_t g = map[rowidx[f]];
                 if (g >= 0) {
                     L[f] = fma(-L[g], lji, L[f]);
-                    ++updates;
+                    if (lji != 0.0) ++updates;
                 }
             }
         }
