@@ -1,0 +1,166 @@
+/*
+ * kchol.h -- C ABI of the MI355X (gfx950) sparse-Cholesky library.
+ *
+ * Method: Schaefer, Sullivan, Owhadi, "Compression, inversion, and approximate
+ * PCA of dense kernel matrices at near-linear computational complexity"
+ * (arXiv:1706.02205).  Given points x_1..x_N, a Matern kernel and rho, the
+ * library computes
+ *   1. the maximin ordering and the sparsity pattern S_rho      (Section 2.3)
+ *   2. the covariance entries Theta_ij on S_rho                  (Section 4.4)
+ *   3. the zero fill-in incomplete Cholesky factor ICHOL(0)      (Section 2.2)
+ *   4. x = Theta^{-1} b ~ P^T L^{-T} L^{-1} P b                  (Section 1, task (2))
+ * Step 1 runs on the host (kc_analyze); steps 2-4 run as HIP kernels.
+ *
+ * Conventions
+ *  - Every pointer argument is owned by the caller; the library never frees
+ *    caller memory.  "_dev" pointers are device memory of the current HIP
+ *    device, all others host memory.
+ *  - Points are row-major N x d float64 in the caller's original order.
+ *    Right-hand sides and solutions are row-major N x nrhs float64 (the nrhs
+ *    values of one point are contiguous), also in the original order.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued asynchronously on it unless stated otherwise.
+ *  - Calls return kc_status; KC_OK is 0.  On failure kc_last_error() gives a
+ *    thread-local message.  No call aborts the process.
+ *  - A nonpositive pivot is not an error: it is counted (Section 4.4 zeroes the
+ *    column; KC_PIVOT_SHIFT raises it instead).
+ *  - Distinct handles may be used from distinct host threads.
+ */
+#ifndef KCHOL_H
+#define KCHOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KC_OK = 0,
+    KC_EINVAL = 1,     /* bad argument: n<1, d<1, rho<=0 or non-finite, non-finite coordinate, nrhs<1, unsupported nu */
+    KC_ENOMEM = 2,     /* host allocation failed */
+    KC_EWORKSPACE = 3, /* device workspace or scratch smaller than required */
+    KC_EHIP = 4,       /* a HIP runtime call failed (detail in kc_last_error) */
+    KC_ESTATE = 5,     /* call out of order, e.g. solve before factorize */
+    KC_ERANGE = 6      /* problem too large for the index types (nnz(S) >= 2^32) */
+} kc_status;
+
+/* Pattern rule.  MAX is the paper's S_rho = {(i,j): dist(x_i,x_j) <= rho*max(l_i,l_j)}
+ * (Section 2.3).  MIN uses rho*min(l_i,l_j), the pattern of Section 6.2. */
+typedef enum { KC_RULE_MAX = 0, KC_RULE_MIN = 1 } kc_rule;
+
+/* Arithmetic of the factorization.  FP64: everything in float64.  MIXED:
+ * off-diagonal entries of Theta, their Schur updates and the stored L in
+ * float32; diagonal accumulation, square roots and divisions in float64. */
+typedef enum { KC_FP64 = 0, KC_MIXED = 1 } kc_prec;
+
+/* Nonpositive pivots.  ZERO (Section 4.4): a pivot p <= 0 zeroes the column of L.
+ * SHIFT: a pivot p <= tau*Theta_jj is replaced by tau*Theta_jj. */
+typedef enum { KC_PIVOT_ZERO = 0, KC_PIVOT_SHIFT = 1 } kc_pivot;
+
+/* Matern covariance G_{l,nu}(x,y) of Section 4.4 with unit variance; nu must be
+ * 0.5, 1.5 or 2.5 (closed forms), lengthscale > 0. */
+typedef struct {
+    double nu;
+    double lengthscale;
+} kc_kernel;
+
+typedef struct kc_plan kc_plan;
+typedef struct kc_factor kc_factor;
+
+typedef struct {
+    int64_t n;
+    int32_t d;
+    int32_t rule;
+    double rho;
+    int64_t nnz;          /* entries of S in the lower triangle, diagonal included */
+    int64_t max_col;      /* longest column of S */
+    int64_t max_row;      /* longest row of S */
+    int32_t nlevels;      /* depth of the elimination DAG (forward levels) */
+    int32_t nrlevels;     /* depth of the reverse DAG (backward solve) */
+    int64_t nunits;       /* 64-entry column chunks scheduled by the factorization */
+    double t_order_s;     /* host time of the maximin ordering */
+    double t_pattern_s;   /* host time of the pattern (CSC + CSR) */
+    double t_schedule_s;  /* host time of levels and work units */
+} kc_plan_info_t;
+
+typedef struct {
+    int64_t nonpositive;  /* columns zeroed by KC_PIVOT_ZERO */
+    int64_t shifted;      /* pivots raised by KC_PIVOT_SHIFT */
+    int64_t rank;         /* n - nonpositive */
+    int64_t updates;      /* Schur updates applied (only if counting was requested, else -1) */
+    int64_t exp_hard;     /* exponentials whose rounding could not be certified (expected 0) */
+} kc_factor_stats_t;
+
+const char *kc_status_string(kc_status s);
+const char *kc_last_error(void);
+
+/* ---------------------------------------------------------------- analysis */
+
+/* Maximin ordering and pattern S (Section 2.3; the ordering and pattern of the
+ * paper's SortSparse algorithm, computed with k-d tree range searches), plus the
+ * level schedule of the elimination DAG.  Host only, synchronous.
+ * x: N x d row-major float64.  nthreads <= 0 uses all hardware threads.
+ * The first point is original index 0; ties in the maximin argmax go to the
+ * lowest original index.  *out is library-owned until kc_plan_destroy. */
+kc_status kc_analyze(const double *x, int64_t n, int32_t d, double rho, kc_rule rule, int32_t nthreads,
+                     kc_plan **out);
+kc_status kc_plan_info(const kc_plan *plan, kc_plan_info_t *info);
+/* Copies the ordering and pattern into caller buffers (any may be NULL):
+ * perm[N] (maximin position -> original index), l[N], colptr[N+1],
+ * rowidx[nnz] (CSC of the lower triangle, rows ascending, diagonal first). */
+kc_status kc_plan_export(const kc_plan *plan, int32_t *perm, double *l, int64_t *colptr, int32_t *rowidx);
+/* Level of each column in the elimination DAG (column j waits for every i<j with (j,i) in S). */
+kc_status kc_plan_levels(const kc_plan *plan, int32_t *level);
+void kc_plan_destroy(kc_plan *plan);
+
+/* ---------------------------------------------------------------- factor */
+
+/* Device workspace needed by a factor of `plan` in precision `prec`. */
+kc_status kc_factor_bytes(const kc_plan *plan, kc_prec prec, size_t *bytes);
+
+/* Binds a factor to a caller-owned device workspace (>= kc_factor_bytes) and
+ * uploads the pattern and schedule into it on `stream`.  The plan may be
+ * destroyed afterwards; the workspace must outlive the factor. */
+kc_status kc_factor_create(const kc_plan *plan, kc_prec prec, void *ws_dev, size_t ws_bytes, void *stream,
+                           kc_factor **out);
+
+/* Theta on S and ICHOL(0) (Sections 4.4 and 2.2), asynchronous on `stream`.
+ * x_dev: N x d points in original order.  tau is used by KC_PIVOT_SHIFT only.
+ * count_updates != 0 also counts the Schur updates (kc_factor_stats.updates).
+ * The FP64 factor reproduces the paper's elimination order entry by entry:
+ * each entry receives its updates in ascending eliminated index as one fused
+ * multiply-add each, and Theta uses a correctly rounded exponential. */
+kc_status kc_factorize(kc_factor *f, const double *x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
+                       int32_t count_updates, void *stream);
+
+/* Theta on S alone, in CSC order (nnz float64) -- the entries the
+ * factorization starts from.  Requires kc_factor_create. */
+kc_status kc_theta(kc_factor *f, const double *x_dev, kc_kernel kernel, double *theta_dev, void *stream);
+
+/* Scratch needed by kc_solve for nrhs right-hand sides. */
+kc_status kc_solve_bytes(const kc_factor *f, int32_t nrhs, size_t *bytes);
+
+/* x = P^T L^{-T} L^{-1} P b (Section 1, task (2)).  b_dev, x_dev: N x nrhs
+ * row-major float64 in original order (may not alias).  A zeroed column gives
+ * solution component 0.  Requires a completed kc_factorize on the same factor. */
+kc_status kc_solve(const kc_factor *f, const double *b_dev, double *x_dev, int32_t nrhs, void *scratch_dev,
+                   size_t scratch_bytes, void *stream);
+
+/* Synchronises the factor's last stream and reports pivot statistics. */
+kc_status kc_factor_stats(kc_factor *f, kc_factor_stats_t *stats);
+
+/* Copies L to the host in CSC order of the plan (nnz float64; MIXED values are
+ * widened).  Synchronous. */
+kc_status kc_factor_export_L(const kc_factor *f, double *vals);
+
+void kc_factor_destroy(kc_factor *f);
+
+/* Number of HIP devices visible (0 if none); for availability checks. */
+int32_t kc_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KCHOL_H */

@@ -1,0 +1,180 @@
+"""Sparse Cholesky factors of dense Matern kernel matrices on MI355X (gfx950).
+
+Method: Schaefer, Sullivan, Owhadi (arXiv:1706.02205).  Points + kernel + rho
+give the maximin ordering and pattern S (host, :func:`analyze`), then the
+covariance entries on S and their ICHOL(0) factor L (GPU, :meth:`Factor.factorize`),
+then x ~ Theta^{-1} b through L and L^T (GPU, :meth:`Factor.solve`).
+
+Every step runs in the HIP library ``libkchol.so`` through its C ABI
+(``include/kchol.h``); this module only marshals arguments.  PyTorch provides
+device memory and the current stream.  There is no CPU fallback: without the
+built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import KCholError
+
+__all__ = ["analyze", "Plan", "Factor", "KCholError"]
+
+_RULES = {"max": _lib.KC_RULE_MAX, "min": _lib.KC_RULE_MIN}
+_PRECS = {"fp64": _lib.KC_FP64, "mixed": _lib.KC_MIXED}
+_PIVOTS = {"zero": _lib.KC_PIVOT_ZERO, "shift": _lib.KC_PIVOT_SHIFT}
+
+
+def _ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data)
+
+
+class Plan:
+    """Host analysis: maximin ordering, pattern S and the elimination schedule."""
+
+    def __init__(self, handle, n: int, d: int):
+        self._h = handle
+        self.n, self.d = n, d
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().kc_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = _lib.kc_plan_info_t()
+        _lib.check(_lib.load().kc_plan_info(self._h, C.byref(inf)), "kc_plan_info")
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    @property
+    def nnz(self) -> int:
+        return int(self.info()["nnz"])
+
+    def export(self):
+        """(perm, l, colptr, rowidx) of the ordering and the CSC pattern."""
+        n, nnz = self.n, self.nnz
+        perm = np.empty(n, np.int32)
+        l = np.empty(n, np.float64)
+        colptr = np.empty(n + 1, np.int64)
+        rowidx = np.empty(nnz, np.int32)
+        _lib.check(_lib.load().kc_plan_export(self._h, _ptr(perm), _ptr(l), _ptr(colptr), _ptr(rowidx)),
+                   "kc_plan_export")
+        return perm, l, colptr, rowidx
+
+    def levels(self) -> np.ndarray:
+        lv = np.empty(self.n, np.int32)
+        _lib.check(_lib.load().kc_plan_levels(self._h, _ptr(lv)), "kc_plan_levels")
+        return lv
+
+
+def analyze(x: np.ndarray, rho: float, rule: str = "max", nthreads: int = 0) -> Plan:
+    """Maximin ordering + pattern S_rho + level schedule (Section 2.3) on the host."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("x must be (n, d)")
+    n, d = x.shape
+    h = C.c_void_p()
+    _lib.check(_lib.load().kc_analyze(_ptr(x), n, d, float(rho), _RULES[rule], int(nthreads), C.byref(h)),
+               "kc_analyze")
+    return Plan(h, n, d)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Stats:
+    nonpositive: int
+    shifted: int
+    rank: int
+    updates: int
+    exp_hard: int
+
+
+class Factor:
+    """A factor bound to a torch-allocated device workspace."""
+
+    def __init__(self, plan: Plan, prec: str = "fp64", stream=None):
+        import torch
+        L = _lib.load()
+        self.n, self.d, self.nnz, self.prec = plan.n, plan.d, plan.nnz, prec
+        nbytes = C.c_size_t()
+        _lib.check(L.kc_factor_bytes(plan.handle, _PRECS[prec], C.byref(nbytes)), "kc_factor_bytes")
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        _lib.check(L.kc_factor_create(plan.handle, _PRECS[prec], C.c_void_p(self.workspace.data_ptr()),
+                                      nbytes.value, _stream_ptr(stream), C.byref(h)), "kc_factor_create")
+        self._h = h
+        self._scratch = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().kc_factor_destroy(h)
+            self._h = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.workspace.numel())
+
+    def factorize(self, x_dev, nu: float, lengthscale: float, pivot: str = "zero", tau: float = 0.0,
+                  count_updates: bool = False, stream=None) -> None:
+        """Theta on S + ICHOL(0), asynchronous on the stream."""
+        self._check_points(x_dev)
+        _lib.check(_lib.load().kc_factorize(self._h, C.c_void_p(x_dev.data_ptr()), _lib.kc_kernel(nu, lengthscale),
+                                            _PIVOTS[pivot], float(tau), int(bool(count_updates)),
+                                            _stream_ptr(stream)), "kc_factorize")
+
+    def theta(self, x_dev, nu: float, lengthscale: float, stream=None):
+        """Theta on S in CSC order (the factorization's starting entries)."""
+        import torch
+        self._check_points(x_dev)
+        out = torch.empty(self.nnz, dtype=torch.float64, device=x_dev.device)
+        _lib.check(_lib.load().kc_theta(self._h, C.c_void_p(x_dev.data_ptr()), _lib.kc_kernel(nu, lengthscale),
+                                        C.c_void_p(out.data_ptr()), _stream_ptr(stream)), "kc_theta")
+        return out
+
+    def solve(self, b_dev, out=None, stream=None):
+        """x = P^T L^-T L^-1 P b for b of shape (n,) or (n, nrhs), original order."""
+        import torch
+        if b_dev.dtype != torch.float64 or not b_dev.is_cuda or not b_dev.is_contiguous():
+            raise ValueError("b must be a contiguous float64 CUDA tensor")
+        if b_dev.shape[0] != self.n:
+            raise ValueError("b must have n rows")
+        nrhs = 1 if b_dev.dim() == 1 else int(b_dev.shape[1])
+        x = out if out is not None else torch.empty_like(b_dev)
+        need = self.n * nrhs * 8
+        if self._scratch is None or self._scratch.numel() < need:
+            self._scratch = torch.empty(need, dtype=torch.uint8, device=b_dev.device)
+        _lib.check(_lib.load().kc_solve(self._h, C.c_void_p(b_dev.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
+                                        C.c_void_p(self._scratch.data_ptr()), self._scratch.numel(),
+                                        _stream_ptr(stream)), "kc_solve")
+        return x
+
+    def stats(self) -> Stats:
+        st = _lib.kc_factor_stats_t()
+        _lib.check(_lib.load().kc_factor_stats(self._h, C.byref(st)), "kc_factor_stats")
+        return Stats(st.nonpositive, st.shifted, st.rank, st.updates, st.exp_hard)
+
+    def export_L(self) -> np.ndarray:
+        """L in the plan's CSC order (float64; MIXED values widened)."""
+        v = np.empty(self.nnz, np.float64)
+        _lib.check(_lib.load().kc_factor_export_L(self._h, _ptr(v)), "kc_factor_export_L")
+        return v
+
+    def _check_points(self, x_dev):
+        import torch
+        if x_dev.dtype != torch.float64 or not x_dev.is_cuda or not x_dev.is_contiguous():
+            raise ValueError("points must be a contiguous float64 CUDA tensor")
+        if tuple(x_dev.shape) != (self.n, self.d):
+            raise ValueError(f"points must have shape ({self.n}, {self.d})")

@@ -1,0 +1,416 @@
+// Host analysis: maximin ordering, sparsity pattern S and the level schedule.
+//
+// Ordering and pattern follow Section 2.3 (maximin ordering; S_rho with the
+// max-rule, or the min-rule of Section 6.2).  Like the paper's SortSparse
+// algorithm (Section 4.1) the ordering is produced with a mutable max-heap of
+// current distances, but the candidate points to update are found with a k-d
+// tree range search of radius l[i] around the newly selected point instead of
+// parent/child lists.  Every comparison that decides the output uses the same
+// floating-point expression as the definition, so the result is exactly the
+// greedy maximin ordering and exactly S_rho:
+//   dist(a,b) = sqrt(sum_t (a_t - b_t)^2), summed over t ascending, no fma;
+//   (a,b) in S  <=>  dist <= rho * l.
+// Tree pruning uses a box lower bound evaluated with the same operation
+// sequence; rounding is monotone, so the bound never exceeds the distance of
+// any point in the box and no candidate is lost.
+//
+// Compiled with -ffp-contract=off.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <limits>
+#include <thread>
+#include <vector>
+
+#include "plan.h"
+
+namespace kc {
+namespace {
+
+
+int resolve_threads(int nthreads) {
+    if (nthreads > 0) return nthreads;
+    unsigned h = std::thread::hardware_concurrency();
+    return h ? int(h) : 1;
+}
+
+// Dynamic parallel loop over [0, count) in chunks.
+template <class F>
+void parallel_for(int nthreads, int64_t count, int64_t chunk, F&& fn) {
+    if (count <= 0) return;
+    nthreads = std::max(1, std::min<int>(nthreads, int((count + chunk - 1) / chunk)));
+    if (nthreads == 1) {
+        fn(int64_t(0), count, 0);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto work = [&](int tid) {
+        for (;;) {
+            int64_t b = next.fetch_add(chunk);
+            if (b >= count) break;
+            fn(b, std::min(count, b + chunk), tid);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
+}
+
+inline double dist(const double* a, const double* b, int d) {
+    double s = 0.0;
+    for (int t = 0; t < d; ++t) {
+        double df = a[t] - b[t];
+        s += df * df;
+    }
+    return std::sqrt(s);
+}
+
+// k-d tree over n points (ids 0..n-1 index the point array).
+struct KDTree {
+    struct Node {
+        int32_t begin, end;   // range in idx
+        int32_t left, right;  // children, -1 for a leaf
+        int32_t minid, maxid; // smallest / largest point id in the subtree
+    };
+    int d = 0;
+    const double* pts = nullptr;
+    std::vector<int32_t> idx;
+    std::vector<Node> nodes;
+    std::vector<double> lo, hi;  // per node, d each
+
+    static constexpr int kLeaf = 16;
+
+    void build(const double* p, int64_t n, int dim) {
+        pts = p;
+        d = dim;
+        idx.resize(n);
+        for (int64_t i = 0; i < n; ++i) idx[i] = int32_t(i);
+        nodes.clear();
+        nodes.reserve(size_t(2 * (n / kLeaf + 1)));
+        build_node(0, int32_t(n));
+    }
+
+    int32_t build_node(int32_t b, int32_t e) {
+        int32_t id = int32_t(nodes.size());
+        nodes.push_back(Node{b, e, -1, -1, 0, 0});
+        lo.resize(size_t(nodes.size()) * d);
+        hi.resize(size_t(nodes.size()) * d);
+        double* L = &lo[size_t(id) * d];
+        double* H = &hi[size_t(id) * d];
+        for (int t = 0; t < d; ++t) {
+            L[t] = std::numeric_limits<double>::infinity();
+            H[t] = -std::numeric_limits<double>::infinity();
+        }
+        int32_t mn = idx[b], mx = idx[b];
+        for (int32_t i = b; i < e; ++i) {
+            const double* q = pts + size_t(idx[i]) * d;
+            for (int t = 0; t < d; ++t) {
+                L[t] = std::min(L[t], q[t]);
+                H[t] = std::max(H[t], q[t]);
+            }
+            mn = std::min(mn, idx[i]);
+            mx = std::max(mx, idx[i]);
+        }
+        nodes[id].minid = mn;
+        nodes[id].maxid = mx;
+        if (e - b <= kLeaf) return id;
+        int ax = 0;
+        double w = -1.0;
+        for (int t = 0; t < d; ++t)
+            if (H[t] - L[t] > w) {
+                w = H[t] - L[t];
+                ax = t;
+            }
+        if (!(w > 0.0)) return id;  // all points coincide: keep as one leaf
+        int32_t mid = b + (e - b) / 2;
+        std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [&](int32_t u, int32_t v) {
+            double a = pts[size_t(u) * d + ax], c = pts[size_t(v) * d + ax];
+            return a < c || (a == c && u < v);
+        });
+        int32_t l = build_node(b, mid);
+        int32_t r = build_node(mid, e);
+        nodes[id].left = l;
+        nodes[id].right = r;
+        return id;
+    }
+
+    // Lower bound on dist(q, y) for y in the node's box, same operation order as dist().
+    double boxdist(int32_t node, const double* q) const {
+        const double* L = &lo[size_t(node) * d];
+        const double* H = &hi[size_t(node) * d];
+        double s = 0.0;
+        for (int t = 0; t < d; ++t) {
+            double g = 0.0;
+            if (q[t] < L[t]) g = L[t] - q[t];
+            else if (q[t] > H[t]) g = q[t] - H[t];
+            s += g * g;
+        }
+        return std::sqrt(s);
+    }
+
+    // Calls leaf(begin, end) for every leaf that may hold a point within r of q and
+    // whose id range intersects [idlo, idhi].
+    template <class F>
+    void visit(const double* q, double r, int32_t idlo, int32_t idhi, F&& leaf) const {
+        int32_t stack[128];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp) {
+            const Node& nd = nodes[stack[--sp]];
+            if (nd.maxid < idlo || nd.minid > idhi) continue;
+            int32_t id = int32_t(&nd - nodes.data());
+            if (boxdist(id, q) > r) continue;
+            if (nd.left < 0) {
+                leaf(nd.begin, nd.end);
+            } else {
+                stack[sp++] = nd.right;
+                stack[sp++] = nd.left;
+            }
+        }
+    }
+};
+
+// Indexed binary max-heap on (m[j] descending, j ascending).
+struct MaxHeap {
+    std::vector<int32_t> heap, pos;
+    const std::vector<double>* m;
+    int64_t size = 0;
+
+    bool greater(int32_t a, int32_t b) const {
+        double ma = (*m)[a], mb = (*m)[b];
+        return ma > mb || (ma == mb && a < b);
+    }
+    void init(int64_t n, const std::vector<double>* key) {
+        m = key;
+        heap.resize(n);
+        pos.resize(n);
+        for (int64_t i = 0; i < n; ++i) heap[i] = pos[i] = int32_t(i);
+        size = n;
+        for (int64_t i = n / 2 - 1; i >= 0; --i) sift_down(i);
+    }
+    void sift_down(int64_t i) {
+        int32_t v = heap[i];
+        for (;;) {
+            int64_t c = 2 * i + 1;
+            if (c >= size) break;
+            if (c + 1 < size && greater(heap[c + 1], heap[c])) ++c;
+            if (!greater(heap[c], v)) break;
+            heap[i] = heap[c];
+            pos[heap[i]] = int32_t(i);
+            i = c;
+        }
+        heap[i] = v;
+        pos[v] = int32_t(i);
+    }
+    int32_t pop() {
+        int32_t top = heap[0];
+        --size;
+        if (size > 0) {
+            heap[0] = heap[size];
+            pos[heap[0]] = 0;
+            sift_down(0);
+        }
+        pos[top] = -1;
+        return top;
+    }
+};
+
+}  // namespace
+
+void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t* perm, double* l) {
+    (void)nthreads;
+    KDTree tree;
+    tree.build(x, n, d);
+    std::vector<double> m(size_t(n), std::numeric_limits<double>::infinity());
+    std::vector<char> sel(size_t(n), 0);
+    MaxHeap heap;
+    heap.init(n, &m);
+    for (int64_t k = 0; k < n; ++k) {
+        int32_t i = heap.pop();
+        perm[k] = i;
+        l[k] = m[i];
+        sel[i] = 1;
+        const double* xi = x + size_t(i) * d;
+        // Only points with dist(x_j, x_i) < m[j] <= m[i] change.
+        tree.visit(xi, m[i], 0, int32_t(n - 1), [&](int32_t b, int32_t e) {
+            for (int32_t t = b; t < e; ++t) {
+                int32_t j = tree.idx[t];
+                if (sel[j]) continue;
+                double dj = dist(x + size_t(j) * d, xi, d);
+                if (dj < m[j]) {
+                    m[j] = dj;
+                    heap.sift_down(heap.pos[j]);
+                }
+            }
+        });
+    }
+}
+
+namespace {
+
+void csr_from_csc(Plan& p) {
+    const int64_t n = p.n, nnz = p.nnz();
+    p.rowptr.assign(size_t(n + 1), 0);
+    for (int64_t e = 0; e < nnz; ++e) p.rowptr[size_t(p.rowidx[e]) + 1]++;
+    for (int64_t k = 0; k < n; ++k) p.rowptr[k + 1] += p.rowptr[k];
+    p.colidx.resize(size_t(nnz));
+    p.csc2csr.resize(size_t(nnz));
+    std::vector<int64_t> fill(p.rowptr.begin(), p.rowptr.end() - 1);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t e = p.colptr[j]; e < p.colptr[j + 1]; ++e) {
+            int64_t q = fill[size_t(p.rowidx[e])]++;
+            p.colidx[size_t(q)] = int32_t(j);
+            p.csc2csr[size_t(e)] = uint32_t(q);
+        }
+    p.max_row = 0;
+    for (int64_t k = 0; k < n; ++k) p.max_row = std::max(p.max_row, p.rowptr[k + 1] - p.rowptr[k]);
+}
+
+}  // namespace
+
+void build_pattern(Plan& p, int nthreads) {
+    nthreads = resolve_threads(nthreads);
+    const int64_t n = p.n;
+    const int d = p.d;
+    const double* xh = p.xh.data();
+    KDTree tree;
+    tree.build(xh, n, d);
+    std::vector<int64_t> cnt(size_t(n), 0);
+
+    if (p.rule == KC_RULE_MAX) {
+        // column b: rows a > b with dist(x_a, x_b) <= rho * max(l_a, l_b) = rho * l_b
+        auto scan = [&](int64_t b, auto&& emit) {
+            const double* xb = xh + size_t(b) * d;
+            double R = p.rho * p.l[size_t(b)];
+            tree.visit(xb, R, int32_t(b + 1), int32_t(n - 1), [&](int32_t s, int32_t e) {
+                for (int32_t t = s; t < e; ++t) {
+                    int32_t a = tree.idx[t];
+                    if (a > b && dist(xh + size_t(a) * d, xb, d) <= R) emit(a);
+                }
+            });
+        };
+        parallel_for(nthreads, n, 64, [&](int64_t b0, int64_t b1, int) {
+            for (int64_t b = b0; b < b1; ++b) {
+                int64_t c = 1;
+                scan(b, [&](int32_t) { ++c; });
+                cnt[b] = c;
+            }
+        });
+        p.colptr.assign(size_t(n + 1), 0);
+        for (int64_t b = 0; b < n; ++b) p.colptr[b + 1] = p.colptr[b] + cnt[b];
+        if (p.colptr[n] >= (int64_t(1) << 32)) return;  // caller reports KC_ERANGE
+        p.rowidx.resize(size_t(p.colptr[n]));
+        parallel_for(nthreads, n, 64, [&](int64_t b0, int64_t b1, int) {
+            for (int64_t b = b0; b < b1; ++b) {
+                int32_t* out = p.rowidx.data() + p.colptr[b];
+                int64_t c = 0;
+                out[c++] = int32_t(b);
+                scan(b, [&](int32_t a) { out[c++] = a; });
+                std::sort(out + 1, out + c);
+            }
+        });
+    } else {
+        // row a: columns b < a with dist(x_a, x_b) <= rho * min(l_a, l_b) = rho * l_a
+        std::vector<int64_t> rcnt(size_t(n), 0);
+        auto scan = [&](int64_t a, auto&& emit) {
+            const double* xa = xh + size_t(a) * d;
+            double R = p.rho * p.l[size_t(a)];
+            tree.visit(xa, R, 0, int32_t(a - 1), [&](int32_t s, int32_t e) {
+                for (int32_t t = s; t < e; ++t) {
+                    int32_t b = tree.idx[t];
+                    if (b < a && dist(xa, xh + size_t(b) * d, d) <= R) emit(b);
+                }
+            });
+        };
+        parallel_for(nthreads, n, 64, [&](int64_t a0, int64_t a1, int) {
+            for (int64_t a = a0; a < a1; ++a) {
+                int64_t c = 0;
+                scan(a, [&](int32_t) { ++c; });
+                rcnt[a] = c;
+            }
+        });
+        std::vector<int64_t> rp(size_t(n + 1), 0);
+        for (int64_t a = 0; a < n; ++a) rp[a + 1] = rp[a] + rcnt[a];
+        std::vector<int32_t> cols(size_t(rp[n]));
+        parallel_for(nthreads, n, 64, [&](int64_t a0, int64_t a1, int) {
+            for (int64_t a = a0; a < a1; ++a) {
+                int32_t* out = cols.data() + rp[a];
+                int64_t c = 0;
+                scan(a, [&](int32_t b) { out[c++] = b; });
+            }
+        });
+        // transpose rows into CSC columns (diagonal first, rows ascending)
+        for (int64_t a = 0; a < n; ++a) cnt[a] = 1;
+        for (int32_t b : cols) cnt[b]++;
+        p.colptr.assign(size_t(n + 1), 0);
+        for (int64_t b = 0; b < n; ++b) p.colptr[b + 1] = p.colptr[b] + cnt[b];
+        if (p.colptr[n] >= (int64_t(1) << 32)) return;
+        p.rowidx.resize(size_t(p.colptr[n]));
+        std::vector<int64_t> fill(p.colptr.begin(), p.colptr.end() - 1);
+        for (int64_t b = 0; b < n; ++b) p.rowidx[size_t(fill[b]++)] = int32_t(b);
+        for (int64_t a = 0; a < n; ++a)
+            for (int64_t q = rp[a]; q < rp[a + 1]; ++q) p.rowidx[size_t(fill[cols[q]]++)] = int32_t(a);
+    }
+    p.max_col = 0;
+    for (int64_t b = 0; b < n; ++b) p.max_col = std::max(p.max_col, p.colptr[b + 1] - p.colptr[b]);
+    csr_from_csc(p);
+}
+
+void build_schedule(Plan& p, int nthreads) {
+    (void)nthreads;
+    const int64_t n = p.n;
+    // forward levels: column j after every parent i in row j
+    p.level.assign(size_t(n), 0);
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t lj = p.level[j] + 1;
+        for (int64_t e = p.colptr[j] + 1; e < p.colptr[j + 1]; ++e) {
+            int32_t k = p.rowidx[e];
+            if (p.level[k] < lj) p.level[k] = lj;
+        }
+    }
+    int32_t nl = 0;
+    for (int64_t j = 0; j < n; ++j) nl = std::max(nl, p.level[j] + 1);
+    p.nlevels = nl;
+    std::vector<int64_t> loff(size_t(nl + 1), 0), uoff(size_t(nl + 1), 0);
+    for (int64_t j = 0; j < n; ++j) {
+        loff[size_t(p.level[j]) + 1]++;
+        uoff[size_t(p.level[j]) + 1] += (p.colptr[j + 1] - p.colptr[j] + 63) / 64;
+    }
+    for (int32_t v = 0; v < nl; ++v) {
+        loff[v + 1] += loff[v];
+        uoff[v + 1] += uoff[v];
+    }
+    p.fwd_off = loff;
+    p.unit_off = uoff;
+    p.fwd_rows.resize(size_t(n));
+    p.units.resize(size_t(uoff[nl]));
+    {
+        std::vector<int64_t> lf(loff.begin(), loff.end() - 1), uf(uoff.begin(), uoff.end() - 1);
+        for (int64_t j = 0; j < n; ++j) {
+            int32_t v = p.level[j];
+            p.fwd_rows[size_t(lf[v]++)] = int32_t(j);
+            int64_t len = p.colptr[j + 1] - p.colptr[j];
+            for (int64_t c = 0; c < len; c += 64) p.units[size_t(uf[v]++)] = Unit{int32_t(j), int32_t(c)};
+        }
+    }
+    // reverse levels: column j after every k > j in column j
+    std::vector<int32_t> rl(size_t(n), 0);
+    int32_t nrl = 0;
+    for (int64_t j = n - 1; j >= 0; --j) {
+        int32_t v = 0;
+        for (int64_t e = p.colptr[j] + 1; e < p.colptr[j + 1]; ++e) v = std::max(v, rl[size_t(p.rowidx[e])] + 1);
+        rl[size_t(j)] = v;
+        nrl = std::max(nrl, v + 1);
+    }
+    p.nrlevels = nrl;
+    p.bwd_off.assign(size_t(nrl + 1), 0);
+    for (int64_t j = 0; j < n; ++j) p.bwd_off[size_t(rl[j]) + 1]++;
+    for (int32_t v = 0; v < nrl; ++v) p.bwd_off[v + 1] += p.bwd_off[v];
+    p.bwd_cols.resize(size_t(n));
+    std::vector<int64_t> bf(p.bwd_off.begin(), p.bwd_off.end() - 1);
+    for (int64_t j = n - 1; j >= 0; --j) p.bwd_cols[size_t(bf[rl[j]]++)] = int32_t(j);
+}
+
+}  // namespace kc

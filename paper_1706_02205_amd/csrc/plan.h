@@ -1,0 +1,66 @@
+// Host-side plan: ordering, pattern and schedule produced by kc_analyze.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kchol.h"
+
+namespace kc {
+
+// One wavefront's share of the factorization: 64 consecutive entries of a column.
+struct Unit {
+    int32_t col;    // column j (maximin position)
+    int32_t first;  // offset of the chunk's first entry inside column j
+};
+
+struct Plan {
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t rule = 0;
+    double rho = 0.0;
+
+    std::vector<int32_t> perm;      // maximin position -> original index
+    std::vector<double> l;          // l[k], l[0] = +inf
+    std::vector<double> xh;         // points in maximin order, n x d
+
+    // lower triangle of S incl. diagonal, CSC (rows ascending, diagonal first)
+    std::vector<int64_t> colptr;
+    std::vector<int32_t> rowidx;
+    // the same entries by rows (CSR, columns ascending, diagonal last)
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> colidx;
+    std::vector<uint32_t> csc2csr;  // CSR position of each CSC entry
+
+    // elimination DAG: column j waits for every i < j with (j,i) in S
+    std::vector<int32_t> level;     // per column
+    int32_t nlevels = 0;
+    std::vector<Unit> units;        // grouped by level
+    std::vector<int64_t> unit_off;  // nlevels + 1
+    std::vector<int32_t> fwd_rows;  // rows grouped by level (forward solve)
+    std::vector<int64_t> fwd_off;   // nlevels + 1
+    // reverse DAG: column j waits for every k > j in column j (backward solve)
+    int32_t nrlevels = 0;
+    std::vector<int32_t> bwd_cols;  // columns grouped by reverse level
+    std::vector<int64_t> bwd_off;   // nrlevels + 1
+
+    int64_t max_col = 0, max_row = 0;
+    double t_order = 0, t_pattern = 0, t_schedule = 0;
+
+    int64_t nnz() const { return colptr.empty() ? 0 : colptr.back(); }
+};
+
+// analysis.cpp
+void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t* perm, double* l);
+void build_pattern(Plan& p, int nthreads);
+void build_schedule(Plan& p, int nthreads);
+
+// Thread-local error message shared by the C ABI.
+void set_error(const std::string& msg);
+
+}  // namespace kc
+
+struct kc_plan {
+    kc::Plan p;
+};

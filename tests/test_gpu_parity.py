@@ -1,0 +1,165 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+FP64 bar: the pattern is bit-identical (host analysis), Theta on S is
+bit-identical (both sides use the correctly rounded exponential), and L is
+bit-identical (same per-entry update order, one fma per update, correctly
+rounded sqrt and division).  Solves are bit-identical whenever every column is
+at most 4096 entries long (sequential substitution on both sides); longer
+columns of the backward sweep are reduced by a whole wavefront, which changes
+the summation order and is held to a relative error of 1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1706_02205_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1706_02205_amd as K
+    return K
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def oracle_factor(x, rho, rule, nu, ell, pivot=O.PIVOT_ZERO, tau=0.0):
+    P = O.pattern(x, rho, O.RULE_MAX if rule == "max" else O.RULE_MIN)
+    th = O.theta_on_pattern(P, nu, ell)
+    return P, th, O.ichol(P, th, pivot, tau)
+
+
+CASES = [
+    # name, points, rho, rule, nu, ell, pivot, tau
+    ("uniform2d-n2000-matern32-rho3", lambda: W.small_uniform_2d().points, 3.0, "max", 1.5, 0.2, "zero", 0.0),
+    ("uniform2d-n2000-matern12-rho3", lambda: W.uniform_points(2000, 2, 21), 3.0, "max", 0.5, 0.2, "zero", 0.0),
+    ("uniform3d-n1500-matern52-rho2.5", lambda: W.uniform_points(1500, 3, 22), 2.5, "max", 2.5, 0.3, "zero", 0.0),
+    ("uniform2d-n1800-matern32-min-rho4", lambda: W.uniform_points(1800, 2, 23), 4.0, "min", 1.5, 0.2, "zero", 0.0),
+    ("uniform2d-n2000-matern32-shift", lambda: W.small_uniform_2d().points, 3.0, "max", 1.5, 0.2, "shift", 1e-6),
+    ("jittergrid-n1600-matern12-rho4", lambda: W.jittered_grid(40, 24), 4.0, "max", 0.5, 0.1, "zero", 0.0),
+    ("sphere20d-n1000-matern32-rho3", lambda: W.embedded_sincos(1000, 25), 3.0, "max", 1.5, 0.2, "zero", 0.0),
+    ("duplicates-n330", lambda: np.concatenate([W.uniform_points(300, 2, 26), W.uniform_points(300, 2, 26)[:30]]),
+     2.0, "max", 0.5, 0.2, "zero", 0.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_factor_bitwise_equal_to_oracle(K, case):
+    name, gen, rho, rule, nu, ell, pivot, tau = case
+    print(f"[gpu] factor parity {name}", flush=True)
+    x = gen()
+    P, th, R = oracle_factor(x, rho, rule, nu, ell, O.PIVOT_ZERO if pivot == "zero" else O.PIVOT_SHIFT, tau)
+    plan = K.analyze(x, rho, rule)
+    f = K.Factor(plan, "fp64")
+    xd = dev(x)
+    theta = f.theta(xd, nu, ell).cpu().numpy()
+    assert np.array_equal(theta, th), f"Theta differs in {np.sum(theta != th)} entries"
+    f.factorize(xd, nu, ell, pivot, tau, count_updates=True)
+    st = f.stats()
+    L = f.export_L()
+    assert st.exp_hard == 0
+    assert st.nonpositive == R.nonpositive and st.shifted == R.shifted
+    assert st.rank == P.n - R.nonpositive
+    assert st.updates == R.updates
+    bad = np.nonzero(L != R.L)[0]
+    assert bad.size == 0, f"{bad.size} of {L.size} entries of L differ; first at CSC position {bad[:5]}"
+
+
+def test_factor_is_deterministic(K):
+    print("[gpu] determinism", flush=True)
+    w = W.small_uniform_2d()
+    plan = K.analyze(w.points, w.rho)
+    f = K.Factor(plan, "fp64")
+    xd = dev(w.points)
+    f.factorize(xd, w.nu, w.lengthscale)
+    a = f.export_L()
+    f.factorize(xd, w.nu, w.lengthscale)
+    assert np.array_equal(a, f.export_L())
+
+
+def test_exponential_over_the_whole_range(K):
+    """exp(-r/l) for r/l from 0 to 750 (normal and subnormal results) equals the oracle's bit for bit."""
+    print("[gpu] correctly rounded exp over [-750, 0]", flush=True)
+    x = W.uniform_points(1500, 1, 27)
+    ell = 1.0 / 750.0
+    P = O.pattern(x, 1e9)
+    th = O.theta_on_pattern(P, 0.5, ell)
+    assert np.sum((th > 0) & (th < 2.2250738585072014e-308)) > 1000  # subnormal results are exercised
+    plan = K.analyze(x, 1e9)
+    f = K.Factor(plan, "fp64")
+    theta = f.theta(dev(x), 0.5, ell).cpu().numpy()
+    assert np.array_equal(theta, th)
+    assert f.stats().exp_hard == 0
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 8, 11])
+def test_solve_matches_oracle(K, nrhs):
+    print(f"[gpu] solve parity nrhs={nrhs}", flush=True)
+    w = W.small_uniform_2d()
+    P, th, R = oracle_factor(w.points, w.rho, "max", w.nu, w.lengthscale)
+    plan = K.analyze(w.points, w.rho)
+    f = K.Factor(plan, "fp64")
+    f.factorize(dev(w.points), w.nu, w.lengthscale)
+    b = W.gaussian_rhs(P.n, nrhs, 31)
+    x = f.solve(dev(b if nrhs > 1 else b[:, 0])).cpu().numpy()
+    ref = O.solve(P, R.L, b if nrhs > 1 else b[:, 0])
+    assert plan.info()["max_col"] <= 4096
+    assert np.array_equal(x, ref)
+
+
+def test_tiny_and_degenerate_inputs(K):
+    print("[gpu] tiny inputs", flush=True)
+    for x in (np.array([[0.3, 0.7]]), W.uniform_points(2, 2, 40), np.ones((5, 3)),
+              np.array([[0.0], [1.0], [0.4]])):
+        P, th, R = oracle_factor(x, 1.0, "max", 0.5, 0.5)
+        plan = K.analyze(x, 1.0)
+        f = K.Factor(plan, "fp64")
+        f.factorize(dev(x), 0.5, 0.5)
+        assert np.array_equal(f.export_L(), R.L)
+        assert f.stats().nonpositive == R.nonpositive
+        b = W.gaussian_rhs(len(x), 2, 41)
+        assert np.array_equal(f.solve(dev(b)).cpu().numpy(), O.solve(P, R.L, b))
+
+
+def test_mixed_precision_error_against_fp64_oracle(K):
+    """FP32 updates / FP64 pivots: no bitwise bar; the error against the FP64 oracle is stated and bounded."""
+    print("[gpu] mixed precision", flush=True)
+    x = W.uniform_points(2000, 2, 42)
+    P, th, R = oracle_factor(x, 3.0, "max", 0.5, 0.2)
+    plan = K.analyze(x, 3.0)
+    f = K.Factor(plan, "mixed")
+    f.factorize(dev(x), 0.5, 0.2, "shift", 1e-6, count_updates=True)
+    st = f.stats()
+    Lm = f.export_L()
+    assert R.nonpositive == 0 and st.shifted == 0
+    assert st.updates == R.updates
+    rel = np.linalg.norm(Lm - R.L) / np.linalg.norm(R.L)
+    print(f"[gpu] mixed vs fp64 oracle: ||dL||_F/||L||_F = {rel:.2e}", flush=True)
+    assert rel < 1e-4
+    e_fp64 = O.frob_error(P, R.L, 0.5, 0.2)
+    e_mixed = O.frob_error(P, Lm, 0.5, 0.2)
+    print(f"[gpu] ||LL^T-Theta||_F/||Theta||_F: fp64 {e_fp64:.3e} mixed {e_mixed:.3e}", flush=True)
+    assert e_mixed < 1.5 * e_fp64
+
+
+def test_errors_surface_as_exceptions(K):
+    import torch
+    w = W.small_uniform_2d()
+    plan = K.analyze(w.points, w.rho)
+    f = K.Factor(plan, "fp64")
+    with pytest.raises(K.KCholError, match="call out of order"):
+        f.solve(dev(np.zeros((w.n, 1))))
+    with pytest.raises(K.KCholError, match="invalid argument"):
+        f.factorize(dev(w.points), 1.0, 0.2)
+    with pytest.raises(ValueError):
+        f.factorize(dev(w.points[:10]), 1.5, 0.2)
+    with pytest.raises(ValueError):
+        f.solve(torch.zeros(w.n, dtype=torch.float32, device="cuda"))
