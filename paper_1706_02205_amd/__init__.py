@@ -153,7 +153,9 @@ class Factor:
             raise ValueError("b must have n rows")
         nrhs = 1 if b_dev.dim() == 1 else int(b_dev.shape[1])
         x = out if out is not None else torch.empty_like(b_dev)
-        need = self.n * nrhs * 8
+        nb = C.c_size_t()
+        _lib.check(_lib.load().kc_solve_bytes(self._h, nrhs, C.byref(nb)), "kc_solve_bytes")
+        need = int(nb.value)
         if self._scratch is None or self._scratch.numel() < need:
             self._scratch = torch.empty(need, dtype=torch.uint8, device=b_dev.device)
         _lib.check(_lib.load().kc_solve(self._h, C.c_void_p(b_dev.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,

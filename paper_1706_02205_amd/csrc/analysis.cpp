@@ -19,6 +19,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <climits>
 #include <limits>
 #include <thread>
 #include <vector>
@@ -251,11 +252,17 @@ void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t*
 namespace {
 
 void csr_from_csc(Plan& p) {
+    // rows start on multiples of kRowAlign entries and are padded with INT32_MAX
     const int64_t n = p.n, nnz = p.nnz();
+    std::vector<int64_t> len(size_t(n), 0);
+    for (int64_t e = 0; e < nnz; ++e) len[size_t(p.rowidx[e])]++;
     p.rowptr.assign(size_t(n + 1), 0);
-    for (int64_t e = 0; e < nnz; ++e) p.rowptr[size_t(p.rowidx[e]) + 1]++;
-    for (int64_t k = 0; k < n; ++k) p.rowptr[k + 1] += p.rowptr[k];
-    p.colidx.resize(size_t(nnz));
+    p.rowend.resize(size_t(n));
+    for (int64_t k = 0; k < n; ++k) {
+        p.rowend[k] = p.rowptr[k] + len[k];
+        p.rowptr[k + 1] = p.rowptr[k] + (len[k] + kRowAlign - 1) / kRowAlign * kRowAlign;
+    }
+    p.colidx.assign(size_t(p.rowptr[n]), INT32_MAX);
     p.csc2csr.resize(size_t(nnz));
     std::vector<int64_t> fill(p.rowptr.begin(), p.rowptr.end() - 1);
     for (int64_t j = 0; j < n; ++j)
@@ -265,7 +272,7 @@ void csr_from_csc(Plan& p) {
             p.csc2csr[size_t(e)] = uint32_t(q);
         }
     p.max_row = 0;
-    for (int64_t k = 0; k < n; ++k) p.max_row = std::max(p.max_row, p.rowptr[k + 1] - p.rowptr[k]);
+    for (int64_t k = 0; k < n; ++k) p.max_row = std::max(p.max_row, len[k]);
 }
 
 }  // namespace

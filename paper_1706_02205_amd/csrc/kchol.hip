@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <climits>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -33,7 +34,8 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 wavefronts
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int64_t kLongColumn = 4096;          // backward solve: longer columns use a whole wavefront
+constexpr int64_t kLongColumn = 2048;          // backward solve: longer columns are reduced in pieces
+constexpr int64_t kChunk = 2048;               // entries per partial dot product of a long column
 constexpr int kMaxRhsPerPass = 8;
 
 enum Counter { kNonpos = 0, kShifted = 1, kUpdates = 2, kExpHard = 3, kNumCounters = 8 };
@@ -85,57 +87,140 @@ __global__ __launch_bounds__(kBlock) void theta_kernel(const Unit* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// A1+A2 (FP64): Theta on S fused into ICHOL(0), one DAG level per launch.
+// Wave-local LDS ordering: every lane's LDS writes are visible to the other
+// lanes of the same wavefront after this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 16 consecutive entries of a padded row, loaded as whole 64-byte (indices) and
+// 128-/64-byte (values) segments so every fetched sector is consumed at once.
+template <typename VT>
+struct RowWindow {
+    int idx[16];
+    VT val[16];
+    __device__ __forceinline__ void load(const int32_t* __restrict__ colidx, const VT* __restrict__ Lv, int64_t p) {
+        const int4* ip = reinterpret_cast<const int4*>(colidx + p);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int4 v = ip[q];
+            idx[4 * q] = v.x;
+            idx[4 * q + 1] = v.y;
+            idx[4 * q + 2] = v.z;
+            idx[4 * q + 3] = v.w;
+        }
+        if constexpr (sizeof(VT) == 8) {
+            const double2* vp = reinterpret_cast<const double2*>(Lv + p);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                double2 v = vp[q];
+                val[2 * q] = v.x;
+                val[2 * q + 1] = v.y;
+            }
+        } else {
+            const float4* vp = reinterpret_cast<const float4*>(Lv + p);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float4 v = vp[q];
+                val[4 * q] = v.x;
+                val[4 * q + 1] = v.y;
+                val[4 * q + 2] = v.z;
+                val[4 * q + 3] = v.w;
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// A1+A2: Theta on S fused into ICHOL(0), one DAG level per launch.
 //
 // Left-looking form of the paper's incomplete Cholesky: entry (k,j) of column j
 // starts at Theta_kj and receives, for every parent i < j with (j,i) and (k,i)
 // in S, in ascending i, the update A_kj <- fma(-L_ki, L_ji, A_kj) -- the same
 // operations in the same order as the right-looking algorithm of Section 2.2,
-// so the result is bitwise that algorithm's.  All parents of column j lie in
-// earlier levels, so a level's columns are independent.
+// so the FP64 result is bitwise that algorithm's.  All parents of column j lie
+// in earlier levels, so the columns of one level are independent.
 //
-// One wavefront handles 64 consecutive entries of one column (a Unit); every
-// lane owns one entry k.  The wave walks row j's parents (uniform across the
-// wave) while each lane advances a cursor along row k of L (stored by rows), so
-// the matching L_ki is found by a merge of two ascending lists without search.
-// The pivot A_jj is accumulated uniformly by every wave of column j from row j,
-// so chunks of a long column need no inter-wave communication.
-template <int TWONU, bool COUNT>
-__global__ __launch_bounds__(kBlock) void ichol_f64(const Unit* __restrict__ units, int64_t ubeg, int64_t uend,
-                                                    const int64_t* __restrict__ colptr,
-                                                    const int32_t* __restrict__ rowidx,
-                                                    const uint32_t* __restrict__ csc2csr,
-                                                    const int64_t* __restrict__ rowptr,
-                                                    const int32_t* __restrict__ colidx, double* __restrict__ Lv,
-                                                    const double* __restrict__ xh, int d, double ell, int policy,
-                                                    double tau, unsigned long long* __restrict__ counters) {
-    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    int64_t u = ubeg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
-    if (u >= uend) return;
-    int lane = threadIdx.x % kWave;
-    int j = __builtin_amdgcn_readfirstlane(units[u].col);
-    int first = __builtin_amdgcn_readfirstlane(units[u].first);
-    int64_t c1 = colptr[j + 1];
-    int64_t e = colptr[j] + first + lane;
-    bool active = e < c1;
-    int k = active ? rowidx[e] : j;
+// A wavefront owns 64 consecutive entries of one column (a Unit), one entry k
+// per lane.  Row j's parents (indices and L_ji) are staged once in LDS.  Each
+// lane then streams row k of L -- stored by rows, padded to 16-entry windows --
+// from its start up to the entry (k,j), whose position is known from the
+// CSC->CSR map, and merges it against the staged row j with a cursor.  The pivot
+// A_jj is accumulated by every wave of column j from the staged row j, so the
+// chunks of a long column need no communication.
+//
+// VT = double: FP64.  VT = float (MIXED): off-diagonal Theta, updates and the
+// stored L in FP32; the pivot accumulates exact FP32 x FP32 products in FP64,
+// and sqrt and the division by L_jj are FP64.
+template <int TWONU, bool COUNT, typename VT, int WPB>
+__global__ __launch_bounds__(WPB * kWave) void ichol_level(
+    const Unit* __restrict__ units, int64_t ubeg, int64_t uend, const int64_t* __restrict__ colptr,
+    const int32_t* __restrict__ rowidx, const uint32_t* __restrict__ csc2csr, const int64_t* __restrict__ rowptr,
+    const int64_t* __restrict__ rowend, const int32_t* __restrict__ colidx, VT* __restrict__ Lv,
+    VT* __restrict__ Lcsc, double* __restrict__ diag, const double* __restrict__ xh, int d, double ell, int policy,
+    double tau, int cap, unsigned long long* __restrict__ counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    VT* sval = reinterpret_cast<VT*>(smem) + wave * cap;
+    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(WPB) * cap * sizeof(VT)) + wave * cap;
 
-    int hard = 0;
-    double acc = kcdev::matern<TWONU>(kcdev::dist(xh + int64_t(k) * d, xh + int64_t(j) * d, d), ell, hard);
+    const int64_t u = ubeg + int64_t(blockIdx.x) * WPB + wave;
+    const bool valid = u < uend;
+    int j = 0, first = 0, np = 0;
+    int64_t t0 = 0;
+    if (valid) {
+        j = __builtin_amdgcn_readfirstlane(units[u].col);
+        first = __builtin_amdgcn_readfirstlane(units[u].first);
+        t0 = rowptr[j];
+        np = int(rowend[j] - 1 - t0);  // parents of j: row j without its diagonal
+    }
+    for (int t = lane; t < np; t += kWave) {
+        sidx[t] = colidx[t0 + t];
+        sval[t] = Lv[t0 + t];
+    }
+    if (lane == 0) sidx[np] = INT_MAX;  // sentinel ends every cursor walk
+    __syncthreads();
+    if (!valid) return;
+
     double dacc = 1.0;  // Theta_jj
+    for (int t = 0; t < np; ++t) {
+        double v = double(sval[t]);
+        dacc = __builtin_fma(-v, v, dacc);
+    }
 
-    int64_t t0 = rowptr[j], t1 = rowptr[j + 1] - 1;  // parents of j (the diagonal is last)
-    int64_t p = rowptr[k];
-    int ci = colidx[p];
+    const int64_t e = colptr[j] + first + lane;
+    const bool active = e < colptr[j + 1];
+    const int k = active ? rowidx[e] : j;
+    int hard = 0;
+    VT acc;
+    if constexpr (sizeof(VT) == 8)
+        acc = kcdev::matern<TWONU>(kcdev::dist(xh + int64_t(k) * d, xh + int64_t(j) * d, d), ell, hard);
+    else
+        acc = kcdev::matern_f32<TWONU>(float(kcdev::dist(xh + int64_t(k) * d, xh + int64_t(j) * d, d)), float(ell));
+
     unsigned long long hits = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        int i = colidx[t];
-        double lji = Lv[t];
-        dacc = __builtin_fma(-lji, lji, dacc);
-        while (ci < i) ci = colidx[++p];
-        if (ci == i) {
-            acc = __builtin_fma(-Lv[p], lji, acc);
-            if (COUNT && lji != 0.0) ++hits;
+    if (active) {
+        const int64_t pend = csc2csr[e];  // position of (k,j) in row k
+        int q = 0;
+        for (int64_t p = rowptr[k]; p < pend; p += 16) {
+            RowWindow<VT> w;
+            w.load(colidx, Lv, p);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                if (p + t < pend) {
+                    const int i = w.idx[t];
+                    while (sidx[q] < i) ++q;
+                    if (sidx[q] == i) {
+                        const VT lji = sval[q];
+                        if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-w.val[t], lji, acc);
+                        else acc = __builtin_fmaf(-w.val[t], lji, acc);
+                        if (COUNT && lji != VT(0)) ++hits;
+                    }
+                }
+            }
         }
     }
 
@@ -144,188 +229,150 @@ __global__ __launch_bounds__(kBlock) void ichol_f64(const Unit* __restrict__ uni
     if (policy == KC_PIVOT_ZERO) {
         zero = !(piv > 0.0);
     } else {
-        double fl = tau * 1.0;
+        const double fl = tau * 1.0;
         if (!(piv > fl)) {
             piv = fl;
             shifted = true;
         }
     }
-    double ljj = zero ? 0.0 : __builtin_sqrt(piv);
-    if (active) Lv[csc2csr[e]] = zero ? 0.0 : (k == j ? ljj : acc / ljj);
-
+    const double ljj = zero ? 0.0 : __builtin_sqrt(piv);
+    if (active) {
+        VT out;
+        if (zero) out = VT(0);
+        else if (k == j) out = VT(ljj);
+        else if constexpr (sizeof(VT) == 8) out = acc / ljj;
+        else out = float(double(acc) / ljj);
+        Lv[csc2csr[e]] = out;
+        Lcsc[e] = out;
+        if constexpr (sizeof(VT) == 4)
+            if (k == j) diag[j] = ljj;
+    }
     if (first == 0 && lane == 0) {
         if (zero) atomicAdd(counters + kNonpos, 1ull);
         if (shifted) atomicAdd(counters + kShifted, 1ull);
     }
     if (COUNT) {
-        unsigned long long tot = wave_sum(active ? hits : 0ull);
+        const unsigned long long tot = wave_sum(hits);
         if (lane == 0 && tot) atomicAdd(counters + kUpdates, tot);
     }
     if (hard && active) atomicAdd(counters + kExpHard, 1ull);
 }
 
-// A1+A2 (MIXED): off-diagonal Theta, updates and stored L in FP32; the pivot is
-// accumulated in FP64 from exact FP32 x FP32 products; sqrt and division in FP64.
-template <int TWONU, bool COUNT>
-__global__ __launch_bounds__(kBlock) void ichol_mixed(const Unit* __restrict__ units, int64_t ubeg, int64_t uend,
-                                                      const int64_t* __restrict__ colptr,
-                                                      const int32_t* __restrict__ rowidx,
-                                                      const uint32_t* __restrict__ csc2csr,
-                                                      const int64_t* __restrict__ rowptr,
-                                                      const int32_t* __restrict__ colidx, float* __restrict__ Lf,
-                                                      double* __restrict__ diag, const double* __restrict__ xh, int d,
-                                                      double ell, int policy, double tau,
-                                                      unsigned long long* __restrict__ counters) {
-    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    int64_t u = ubeg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
-    if (u >= uend) return;
-    int lane = threadIdx.x % kWave;
-    int j = __builtin_amdgcn_readfirstlane(units[u].col);
-    int first = __builtin_amdgcn_readfirstlane(units[u].first);
-    int64_t c1 = colptr[j + 1];
-    int64_t e = colptr[j] + first + lane;
-    bool active = e < c1;
-    int k = active ? rowidx[e] : j;
-
-    float r = float(kcdev::dist(xh + int64_t(k) * d, xh + int64_t(j) * d, d));
-    float acc = kcdev::matern_f32<TWONU>(r, float(ell));
-    double dacc = 1.0;
-
-    int64_t t0 = rowptr[j], t1 = rowptr[j + 1] - 1;
-    int64_t p = rowptr[k];
-    int ci = colidx[p];
-    unsigned long long hits = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        int i = colidx[t];
-        float lji = Lf[t];
-        dacc = __builtin_fma(-double(lji), double(lji), dacc);
-        while (ci < i) ci = colidx[++p];
-        if (ci == i) {
-            acc = __builtin_fmaf(-Lf[p], lji, acc);
-            if (COUNT && lji != 0.0f) ++hits;
-        }
-    }
-
-    bool zero = false, shifted = false;
-    double piv = dacc;
-    if (policy == KC_PIVOT_ZERO) {
-        zero = !(piv > 0.0);
-    } else {
-        double fl = tau * 1.0;
-        if (!(piv > fl)) {
-            piv = fl;
-            shifted = true;
-        }
-    }
-    double ljj = zero ? 0.0 : __builtin_sqrt(piv);
-    if (active) {
-        float out = zero ? 0.0f : (k == j ? float(ljj) : float(double(acc) / ljj));
-        Lf[csc2csr[e]] = out;
-        if (k == j) diag[j] = ljj;
-    }
-    if (first == 0 && lane == 0) {
-        if (zero) atomicAdd(counters + kNonpos, 1ull);
-        if (shifted) atomicAdd(counters + kShifted, 1ull);
-    }
-    if (COUNT) {
-        unsigned long long tot = wave_sum(active ? hits : 0ull);
-        if (lane == 0 && tot) atomicAdd(counters + kUpdates, tot);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // A3: y = L^{-1} P b by rows (forward levels), x = P^T L^{-T} y by columns
-// (reverse levels).  Each row / short column is one lane that accumulates its
-// right-hand sides in registers in ascending index order, exactly like the
-// sequential substitution; long columns of the backward sweep use a whole
-// wavefront with a fixed-order lane reduction.
+// (reverse levels).  A wavefront owns one row (one column): its lanes stage 64
+// entries at a time in LDS -- the L values and the gathered right-hand-side
+// rows -- and lanes r < NR then apply them to right-hand side r in ascending
+// index order, one fma each, exactly the sequential substitution.  Columns
+// longer than kLongColumn are instead cut into kChunk-entry pieces whose
+// partial dot products are reduced by whole wavefronts and added in a fixed
+// order (deterministic, but summed in a different order than the sequential
+// substitution).
 
 template <typename VT>
-__device__ __forceinline__ double diag_of(const VT* Lv, const double* diag, int64_t rowend, int k) {
-    if constexpr (sizeof(VT) == 8) return Lv[rowend];
+__device__ __forceinline__ double diag_value(const VT* Lv, const double* diag, int64_t pos, int k) {
+    if constexpr (sizeof(VT) == 8) return Lv[pos];
     else return diag[k];
 }
 
 template <typename VT, int NR>
 __global__ __launch_bounds__(kBlock) void fwd_solve(const int32_t* __restrict__ rows, int64_t beg, int64_t end,
                                                     const int64_t* __restrict__ rowptr,
+                                                    const int64_t* __restrict__ rowend,
                                                     const int32_t* __restrict__ colidx, const VT* __restrict__ Lv,
                                                     const double* __restrict__ diag,
                                                     const int32_t* __restrict__ perm, const double* __restrict__ b,
                                                     int ld, int r0, double* __restrict__ y) {
-    int64_t t = beg + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    __shared__ double sL[kWavesPerBlock][kWave];
+    __shared__ double sY[kWavesPerBlock][kWave * NR];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
     if (t >= end) return;
-    int k = rows[t];
-    double acc[NR];
-    const double* bk = b + int64_t(perm[k]) * ld + r0;
+    const int k = __builtin_amdgcn_readfirstlane(rows[t]);
+    const int64_t p0 = rowptr[k], pd = rowend[k] - 1;  // pd: the diagonal
+    double acc = 0.0;
+    if (lane < NR) acc = b[int64_t(perm[k]) * ld + r0 + lane];
+    for (int64_t c = p0; c < pd; c += kWave) {
+        const int64_t p = c + lane;
+        if (p < pd) {
+            sL[wave][lane] = double(Lv[p]);
+            const double* yi = y + int64_t(colidx[p]) * ld + r0;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = bk[r];
-    int64_t p1 = rowptr[k + 1] - 1;
-    for (int64_t p = rowptr[k]; p < p1; ++p) {
-        double l = double(Lv[p]);
-        const double* yi = y + int64_t(colidx[p]) * ld + r0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = __builtin_fma(-l, yi[r], acc[r]);
+            for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = yi[r];
+        }
+        wave_lds_sync();
+        if (lane < NR) {
+            const int m = int(pd - c < kWave ? pd - c : kWave);
+            for (int q = 0; q < m; ++q) acc = __builtin_fma(-sL[wave][q], sY[wave][q * NR + lane], acc);
+        }
+        wave_lds_sync();
     }
-    double lkk = diag_of(Lv, diag, p1, k);
-    double* yk = y + int64_t(k) * ld + r0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) yk[r] = (lkk == 0.0) ? 0.0 : acc[r] / lkk;
-}
-
-template <typename VT, int NR>
-__global__ __launch_bounds__(kBlock) void bwd_solve_short(const int32_t* __restrict__ cols, int64_t beg, int64_t end,
-                                                          const int64_t* __restrict__ colptr,
-                                                          const int32_t* __restrict__ rowidx,
-                                                          const uint32_t* __restrict__ csc2csr,
-                                                          const VT* __restrict__ Lv, const double* __restrict__ diag,
-                                                          const int32_t* __restrict__ perm, int ld, int r0,
-                                                          double* __restrict__ y, double* __restrict__ x) {
-    int64_t t = beg + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= end) return;
-    int j = cols[t];
-    double acc[NR];
-    double* yj = y + int64_t(j) * ld + r0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = yj[r];
-    int64_t c0 = colptr[j], c1 = colptr[j + 1];
-    for (int64_t e = c0 + 1; e < c1; ++e) {
-        double l = double(Lv[csc2csr[e]]);
-        const double* xk = y + int64_t(rowidx[e]) * ld + r0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = __builtin_fma(-l, xk[r], acc[r]);
-    }
-    double ljj;
-    if constexpr (sizeof(VT) == 8) ljj = Lv[csc2csr[c0]];
-    else ljj = diag[j];
-    double* xo = x + int64_t(perm[j]) * ld + r0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        double v = (ljj == 0.0) ? 0.0 : acc[r] / ljj;
-        yj[r] = v;
-        xo[r] = v;
+    if (lane < NR) {
+        const double lkk = diag_value(Lv, diag, pd, k);
+        y[int64_t(k) * ld + r0 + lane] = (lkk == 0.0) ? 0.0 : acc / lkk;
     }
 }
 
 template <typename VT, int NR>
-__global__ __launch_bounds__(kBlock) void bwd_solve_long(const int32_t* __restrict__ cols, int64_t beg, int64_t end,
-                                                         const int64_t* __restrict__ colptr,
-                                                         const int32_t* __restrict__ rowidx,
-                                                         const uint32_t* __restrict__ csc2csr,
-                                                         const VT* __restrict__ Lv, const double* __restrict__ diag,
-                                                         const int32_t* __restrict__ perm, int ld, int r0,
-                                                         double* __restrict__ y, double* __restrict__ x) {
-    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
+__global__ __launch_bounds__(kBlock) void bwd_solve(const int32_t* __restrict__ cols, int64_t beg, int64_t end,
+                                                    const int64_t* __restrict__ colptr,
+                                                    const int32_t* __restrict__ rowidx, const VT* __restrict__ Lcsc,
+                                                    const double* __restrict__ diag,
+                                                    const int32_t* __restrict__ perm, int ld, int r0,
+                                                    double* __restrict__ y, double* __restrict__ x) {
+    __shared__ double sL[kWavesPerBlock][kWave];
+    __shared__ double sY[kWavesPerBlock][kWave * NR];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
     if (t >= end) return;
-    int lane = threadIdx.x % kWave;
-    int j = cols[t];
-    int64_t c0 = colptr[j], c1 = colptr[j + 1];
+    const int j = __builtin_amdgcn_readfirstlane(cols[t]);
+    const int64_t c0 = colptr[j], c1 = colptr[j + 1];
+    double acc = 0.0;
+    if (lane < NR) acc = y[int64_t(j) * ld + r0 + lane];
+    for (int64_t c = c0 + 1; c < c1; c += kWave) {
+        const int64_t e = c + lane;
+        if (e < c1) {
+            sL[wave][lane] = double(Lcsc[e]);
+            const double* xk = y + int64_t(rowidx[e]) * ld + r0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = xk[r];
+        }
+        wave_lds_sync();
+        if (lane < NR) {
+            const int m = int(c1 - c < kWave ? c1 - c : kWave);
+            for (int q = 0; q < m; ++q) acc = __builtin_fma(-sL[wave][q], sY[wave][q * NR + lane], acc);
+        }
+        wave_lds_sync();
+    }
+    if (lane < NR) {
+        const double ljj = diag_value(Lcsc, diag, c0, j);
+        const double v = (ljj == 0.0) ? 0.0 : acc / ljj;
+        y[int64_t(j) * ld + r0 + lane] = v;
+        x[int64_t(perm[j]) * ld + r0 + lane] = v;
+    }
+}
+
+// Partial dot products of long columns: one wavefront per kChunk entries.
+template <typename VT, int NR>
+__global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __restrict__ chunks, int64_t beg,
+                                                      int64_t end, const int64_t* __restrict__ colptr,
+                                                      const int32_t* __restrict__ rowidx,
+                                                      const VT* __restrict__ Lcsc, int ld, int r0,
+                                                      const double* __restrict__ y, double* __restrict__ partial) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    if (t >= end) return;
+    const kc::BwdChunk ch = chunks[t];
+    const int64_t e0 = colptr[ch.col] + 1 + ch.start;
+    const int64_t e1 = e0 + kChunk < colptr[ch.col + 1] ? e0 + kChunk : colptr[ch.col + 1];
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] = 0.0;
-    for (int64_t e = c0 + 1 + lane; e < c1; e += kWave) {
-        double l = double(Lv[csc2csr[e]]);
+    for (int64_t e = e0 + lane; e < e1; e += kWave) {
+        const double l = double(Lcsc[e]);
         const double* xk = y + int64_t(rowidx[e]) * ld + r0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) s[r] = __builtin_fma(l, xk[r], s[r]);
@@ -334,18 +381,35 @@ __global__ __launch_bounds__(kBlock) void bwd_solve_long(const int32_t* __restri
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) s[r] += __shfl_xor(s[r], off, kWave);
-    if (lane == 0) {
-        double ljj;
-        if constexpr (sizeof(VT) == 8) ljj = Lv[csc2csr[c0]];
-        else ljj = diag[j];
-        double* yj = y + int64_t(j) * ld + r0;
-        double* xo = x + int64_t(perm[j]) * ld + r0;
+    if (lane < NR) {
+        double v = s[0];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            double v = (ljj == 0.0) ? 0.0 : (yj[r] - s[r]) / ljj;
-            yj[r] = v;
-            xo[r] = v;
-        }
+        for (int r = 1; r < NR; ++r)
+            if (lane == r) v = s[r];
+        partial[int64_t(ch.slot) * NR + lane] = v;
+    }
+}
+
+// Completes the long columns of a reverse level from their partial sums (fixed order).
+template <typename VT, int NR>
+__global__ __launch_bounds__(kBlock) void bwd_combine(const kc::LongCol* __restrict__ lcols, int64_t beg,
+                                                      int64_t end, const int64_t* __restrict__ colptr,
+                                                      const VT* __restrict__ Lcsc, const double* __restrict__ diag,
+                                                      const int32_t* __restrict__ perm, int ld, int r0,
+                                                      const double* __restrict__ partial, double* __restrict__ y,
+                                                      double* __restrict__ x) {
+    const int64_t t = beg + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= end) return;
+    const kc::LongCol lc = lcols[t];
+    const double ljj = diag_value(Lcsc, diag, colptr[lc.col], lc.col);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        double s = 0.0;
+        for (int q = 0; q < lc.nslots; ++q) s += partial[int64_t(lc.slot0 + q) * NR + r];
+        double* yj = y + int64_t(lc.col) * ld + r0 + r;
+        const double v = (ljj == 0.0) ? 0.0 : (*yj - s) / ljj;
+        *yj = v;
+        x[int64_t(perm[lc.col]) * ld + r0 + r] = v;
     }
 }
 
@@ -379,8 +443,10 @@ void set_error(const std::string& msg) { g_err = msg; }
     } while (0)
 
 struct kc_factor {
-    int64_t n = 0, nnz = 0, nunits = 0;
+    int64_t n = 0, nnz = 0, nnz_rows = 0, nunits = 0;
     int32_t d = 0;
+    int32_t cap = 0;          // LDS entries per wavefront (longest row, rounded up)
+    int32_t wpb = 4;          // wavefronts per block of the factorization kernel
     kc_prec prec = KC_FP64;
     // device regions
     unsigned long long* counters = nullptr;
@@ -390,15 +456,19 @@ struct kc_factor {
     int32_t* rowidx = nullptr;
     uint32_t* csc2csr = nullptr;
     int64_t* rowptr = nullptr;
+    int64_t* rowend = nullptr;
     int32_t* colidx = nullptr;
-    void* L = nullptr;        // double[nnz] or float[nnz]
+    void* L = nullptr;        // by rows: double[nnz_rows] or float[nnz_rows]
+    void* Lcsc = nullptr;     // by columns: double[nnz] or float[nnz]
     double* diag = nullptr;   // MIXED only
     Unit* units = nullptr;
     int32_t* fwd_rows = nullptr;
-    int32_t* bwd_cols = nullptr;
+    int32_t* bwd_short = nullptr;
+    kc::LongCol* bwd_long = nullptr;
+    kc::BwdChunk* bwd_chunks = nullptr;
     // host schedule
-    std::vector<int64_t> unit_off, fwd_off;
-    std::vector<int64_t> bwd_beg, bwd_mid, bwd_end;  // per reverse level: short [beg,mid), long [mid,end)
+    std::vector<int64_t> unit_off, fwd_off, short_off, long_off, chunk_off;
+    int64_t max_slots = 0;    // partial sums needed by the widest reverse level
     bool factorized = false;
     bool counted = false;
     hipStream_t last = nullptr;
@@ -408,11 +478,50 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-struct Layout {
-    size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, colidx, L, diag, units, fwd, bwd, total;
+struct BwdSchedule {
+    std::vector<int32_t> shortc;
+    std::vector<kc::LongCol> longc;
+    std::vector<kc::BwdChunk> chunks;
+    std::vector<int64_t> short_off, long_off, chunk_off;
+    int64_t max_slots = 0;
 };
 
-Layout layout_of(const kc::Plan& p, kc_prec prec) {
+// Reverse levels split into short columns (one wavefront each) and long columns
+// (kChunk-entry pieces plus a combine step).
+BwdSchedule backward_schedule(const kc::Plan& p) {
+    BwdSchedule b;
+    const int32_t nl = p.nrlevels;
+    b.short_off.assign(size_t(nl + 1), 0);
+    b.long_off.assign(size_t(nl + 1), 0);
+    b.chunk_off.assign(size_t(nl + 1), 0);
+    for (int32_t v = 0; v < nl; ++v) {
+        int32_t slot = 0;
+        for (int64_t q = p.bwd_off[v]; q < p.bwd_off[v + 1]; ++q) {
+            const int32_t j = p.bwd_cols[size_t(q)];
+            const int64_t off = p.colptr[j + 1] - p.colptr[j] - 1;  // off-diagonal entries
+            if (off <= kLongColumn) {
+                b.shortc.push_back(j);
+                continue;
+            }
+            const int32_t pieces = int32_t((off + kChunk - 1) / kChunk);
+            b.longc.push_back(kc::LongCol{j, slot, pieces, 0});
+            for (int32_t c = 0; c < pieces; ++c) b.chunks.push_back(kc::BwdChunk{j, int32_t(c * kChunk), slot + c, 0});
+            slot += pieces;
+        }
+        b.max_slots = std::max<int64_t>(b.max_slots, slot);
+        b.short_off[v + 1] = int64_t(b.shortc.size());
+        b.long_off[v + 1] = int64_t(b.longc.size());
+        b.chunk_off[v + 1] = int64_t(b.chunks.size());
+    }
+    return b;
+}
+
+struct Layout {
+    size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, L, Lcsc, diag, units, fwd, bshort,
+        blong, bchunks, total;
+};
+
+Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
     Layout o{};
     size_t at = 0;
     auto take = [&](size_t bytes) {
@@ -420,7 +529,8 @@ Layout layout_of(const kc::Plan& p, kc_prec prec) {
         at = align256(at + bytes);
         return r;
     };
-    const size_t n = size_t(p.n), nnz = size_t(p.nnz());
+    const size_t n = size_t(p.n), nnz = size_t(p.nnz()), nnzr = size_t(p.nnz_rows());
+    const size_t vt = prec == KC_FP64 ? sizeof(double) : sizeof(float);
     o.counters = take(kNumCounters * sizeof(unsigned long long));
     o.xh = take(n * p.d * sizeof(double));
     o.perm = take(n * sizeof(int32_t));
@@ -428,12 +538,16 @@ Layout layout_of(const kc::Plan& p, kc_prec prec) {
     o.rowidx = take(nnz * sizeof(int32_t));
     o.csc2csr = take(nnz * sizeof(uint32_t));
     o.rowptr = take((n + 1) * sizeof(int64_t));
-    o.colidx = take(nnz * sizeof(int32_t));
-    o.L = take(nnz * (prec == KC_FP64 ? sizeof(double) : sizeof(float)));
+    o.rowend = take(n * sizeof(int64_t));
+    o.colidx = take(nnzr * sizeof(int32_t));
+    o.L = take(nnzr * vt);
+    o.Lcsc = take(nnz * vt);
     o.diag = take(prec == KC_FP64 ? 0 : n * sizeof(double));
     o.units = take(p.units.size() * sizeof(Unit));
     o.fwd = take(n * sizeof(int32_t));
-    o.bwd = take(n * sizeof(int32_t));
+    o.bshort = take(b.shortc.size() * sizeof(int32_t));
+    o.blong = take(b.longc.size() * sizeof(kc::LongCol));
+    o.bchunks = take(b.chunks.size() * sizeof(kc::BwdChunk));
     o.total = at;
     return o;
 }
@@ -447,30 +561,67 @@ int twonu_of(double nu) {
 
 unsigned grid_for(int64_t items, int per_block) { return unsigned((items + per_block - 1) / per_block); }
 
-}  // namespace
+// LDS entries per wavefront for staging row j (its parents plus a sentinel).
+int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 1 + 15) / 16 * 16); }
 
-namespace {
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+template <typename VT>
+kc_status launch_level(const kc_factor* f, int tn, bool cnt, int64_t ub, int64_t ue, double ell, int pol, double tau,
+                       hipStream_t s) {
+    VT* Lv = static_cast<VT*>(f->L);
+    VT* Lc = static_cast<VT*>(f->Lcsc);
+    const size_t lds = size_t(f->wpb) * f->cap * (sizeof(VT) + sizeof(int32_t));
+    const dim3 grid(grid_for(ue - ub, f->wpb));
+#define KC_ARGS                                                                                           \
+    f->units, ub, ue, f->colptr, f->rowidx, f->csc2csr, f->rowptr, f->rowend, f->colidx, Lv, Lc, f->diag, \
+        f->xh, f->d, ell, pol, tau, f->cap, f->counters
+#define KC_CASE(TN, C)                                                                                    \
+    if (tn == TN && cnt == C) {                                                                           \
+        if (f->wpb == 4) ichol_level<TN, C, VT, 4><<<grid, 4 * kWave, lds, s>>>(KC_ARGS);                   \
+        else ichol_level<TN, C, VT, 1><<<grid, kWave, lds, s>>>(KC_ARGS);                                  \
+    }
+    KC_CASE(1, false)
+    KC_CASE(1, true)
+    KC_CASE(3, false)
+    KC_CASE(3, true)
+    KC_CASE(5, false)
+    KC_CASE(5, true)
+#undef KC_CASE
+#undef KC_ARGS
+    KC_LAUNCH_CHECK();
+    return KC_OK;
+}
+
 template <typename VT, int NR>
-kc_status solve_pass(const kc_factor* f, const double* b, double* x, int ld, int r0, double* y, hipStream_t s) {
+kc_status solve_pass(const kc_factor* f, const double* b, double* x, int ld, int r0, double* y, double* partial,
+                     hipStream_t s) {
     const VT* Lv = static_cast<const VT*>(f->L);
+    const VT* Lc = static_cast<const VT*>(f->Lcsc);
     const size_t nl = f->fwd_off.size() - 1;
     for (size_t v = 0; v < nl; ++v) {
-        int64_t rb = f->fwd_off[v], re = f->fwd_off[v + 1];
+        const int64_t rb = f->fwd_off[v], re = f->fwd_off[v + 1];
         if (re <= rb) continue;
-        fwd_solve<VT, NR><<<grid_for(re - rb, kBlock), kBlock, 0, s>>>(f->fwd_rows, rb, re, f->rowptr, f->colidx, Lv,
-                                                                        f->diag, f->perm, b, ld, r0, y);
+        fwd_solve<VT, NR><<<grid_for(re - rb, kWavesPerBlock), kBlock, 0, s>>>(
+            f->fwd_rows, rb, re, f->rowptr, f->rowend, f->colidx, Lv, f->diag, f->perm, b, ld, r0, y);
         KC_LAUNCH_CHECK();
     }
-    for (size_t v = 0; v < f->bwd_beg.size(); ++v) {
-        int64_t cb = f->bwd_beg[v], cm = f->bwd_mid[v], ce = f->bwd_end[v];
-        if (cm > cb) {
-            bwd_solve_short<VT, NR><<<grid_for(cm - cb, kBlock), kBlock, 0, s>>>(
-                f->bwd_cols, cb, cm, f->colptr, f->rowidx, f->csc2csr, Lv, f->diag, f->perm, ld, r0, y, x);
+    const size_t nr = f->short_off.size() - 1;
+    for (size_t v = 0; v < nr; ++v) {
+        const int64_t sb = f->short_off[v], se = f->short_off[v + 1];
+        if (se > sb) {
+            bwd_solve<VT, NR><<<grid_for(se - sb, kWavesPerBlock), kBlock, 0, s>>>(
+                f->bwd_short, sb, se, f->colptr, f->rowidx, Lc, f->diag, f->perm, ld, r0, y, x);
             KC_LAUNCH_CHECK();
         }
-        if (ce > cm) {
-            bwd_solve_long<VT, NR><<<grid_for(ce - cm, kWavesPerBlock), kBlock, 0, s>>>(
-                f->bwd_cols, cm, ce, f->colptr, f->rowidx, f->csc2csr, Lv, f->diag, f->perm, ld, r0, y, x);
+        const int64_t cb = f->chunk_off[v], ce = f->chunk_off[v + 1];
+        if (ce > cb) {
+            bwd_partial<VT, NR><<<grid_for(ce - cb, kWavesPerBlock), kBlock, 0, s>>>(
+                f->bwd_chunks, cb, ce, f->colptr, f->rowidx, Lc, ld, r0, y, partial);
+            KC_LAUNCH_CHECK();
+            const int64_t lb = f->long_off[v], le = f->long_off[v + 1];
+            bwd_combine<VT, NR><<<grid_for(le - lb, kBlock), kBlock, 0, s>>>(f->bwd_long, lb, le, f->colptr, Lc,
+                                                                            f->diag, f->perm, ld, r0, partial, y, x);
             KC_LAUNCH_CHECK();
         }
     }
@@ -478,24 +629,31 @@ kc_status solve_pass(const kc_factor* f, const double* b, double* x, int ld, int
 }
 
 template <typename VT>
-kc_status solve_typed(const kc_factor* f, const double* b, double* x, int nrhs, double* y, hipStream_t s) {
+kc_status solve_typed(const kc_factor* f, const double* b, double* x, int nrhs, double* y, double* partial,
+                      hipStream_t s) {
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerPass) {
-        int nr = std::min(kMaxRhsPerPass, nrhs - r0);
+        const int nr = std::min(kMaxRhsPerPass, nrhs - r0);
         kc_status st;
         switch (nr) {
-            case 1: st = solve_pass<VT, 1>(f, b, x, nrhs, r0, y, s); break;
-            case 2: st = solve_pass<VT, 2>(f, b, x, nrhs, r0, y, s); break;
-            case 3: st = solve_pass<VT, 3>(f, b, x, nrhs, r0, y, s); break;
-            case 4: st = solve_pass<VT, 4>(f, b, x, nrhs, r0, y, s); break;
-            case 5: st = solve_pass<VT, 5>(f, b, x, nrhs, r0, y, s); break;
-            case 6: st = solve_pass<VT, 6>(f, b, x, nrhs, r0, y, s); break;
-            case 7: st = solve_pass<VT, 7>(f, b, x, nrhs, r0, y, s); break;
-            default: st = solve_pass<VT, 8>(f, b, x, nrhs, r0, y, s); break;
+            case 1: st = solve_pass<VT, 1>(f, b, x, nrhs, r0, y, partial, s); break;
+            case 2: st = solve_pass<VT, 2>(f, b, x, nrhs, r0, y, partial, s); break;
+            case 3: st = solve_pass<VT, 3>(f, b, x, nrhs, r0, y, partial, s); break;
+            case 4: st = solve_pass<VT, 4>(f, b, x, nrhs, r0, y, partial, s); break;
+            case 5: st = solve_pass<VT, 5>(f, b, x, nrhs, r0, y, partial, s); break;
+            case 6: st = solve_pass<VT, 6>(f, b, x, nrhs, r0, y, partial, s); break;
+            case 7: st = solve_pass<VT, 7>(f, b, x, nrhs, r0, y, partial, s); break;
+            default: st = solve_pass<VT, 8>(f, b, x, nrhs, r0, y, partial, s); break;
         }
         if (st != KC_OK) return st;
     }
     return KC_OK;
 }
+
+size_t solve_scratch_bytes(const kc_factor* f, int32_t nrhs) {
+    return align256(size_t(f->n) * size_t(nrhs) * sizeof(double)) +
+           size_t(std::max<int64_t>(f->max_slots, 1)) * kMaxRhsPerPass * sizeof(double);
+}
+
 }  // namespace
 
 extern "C" {
@@ -508,7 +666,7 @@ const char* kc_status_string(kc_status s) {
         case KC_EWORKSPACE: return "workspace too small";
         case KC_EHIP: return "HIP runtime error";
         case KC_ESTATE: return "call out of order";
-        case KC_ERANGE: return "problem too large for 32-bit entry positions";
+        case KC_ERANGE: return "problem too large for the index types";
     }
     return "unknown status";
 }
@@ -532,8 +690,8 @@ kc_status kc_analyze(const double* x, int64_t n, int32_t d, double rho, kc_rule 
         kc::set_error("kc_analyze: need x != NULL, n >= 1, d >= 1, finite rho > 0, rule MAX or MIN");
         return KC_EINVAL;
     }
-    if (n >= (int64_t(1) << 31)) {
-        kc::set_error("kc_analyze: n must be below 2^31");
+    if (n >= (int64_t(1) << 31) - 1) {
+        kc::set_error("kc_analyze: n must be below 2^31 - 1");
         return KC_ERANGE;
     }
     for (int64_t i = 0; i < n * d; ++i)
@@ -558,7 +716,7 @@ kc_status kc_analyze(const double* x, int64_t n, int32_t d, double rho, kc_rule 
         for (int64_t k = 0; k < n; ++k)
             for (int t = 0; t < d; ++t) p.xh[size_t(k) * d + t] = x[size_t(p.perm[k]) * d + t];
         kc::build_pattern(p, nthreads);
-        if (p.nnz() >= (int64_t(1) << 32)) {
+        if (p.nnz() >= (int64_t(1) << 32) || p.nnz_rows() >= (int64_t(1) << 32)) {
             delete plan;
             kc::set_error("kc_analyze: nnz(S) >= 2^32");
             return KC_ERANGE;
@@ -617,7 +775,7 @@ void kc_plan_destroy(kc_plan* plan) { delete plan; }
 
 kc_status kc_factor_bytes(const kc_plan* plan, kc_prec prec, size_t* bytes) {
     if (!plan || !bytes || (prec != KC_FP64 && prec != KC_MIXED)) return KC_EINVAL;
-    *bytes = layout_of(plan->p, prec).total;
+    *bytes = layout_of(plan->p, backward_schedule(plan->p), prec).total;
     return KC_OK;
 }
 
@@ -630,7 +788,13 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
         return KC_EINVAL;
     }
     const kc::Plan& p = plan->p;
-    Layout o = layout_of(p, prec);
+    BwdSchedule bs;
+    try {
+        bs = backward_schedule(p);
+    } catch (const std::bad_alloc&) {
+        return KC_ENOMEM;
+    }
+    const Layout o = layout_of(p, bs, prec);
     if (ws_bytes < o.total) {
         kc::set_error("kc_factor_create: workspace holds " + std::to_string(ws_bytes) + " bytes, needs " +
                       std::to_string(o.total));
@@ -642,9 +806,19 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     }
     std::unique_ptr<kc_factor> f(new (std::nothrow) kc_factor);
     if (!f) return KC_ENOMEM;
+    const size_t vt = prec == KC_FP64 ? sizeof(double) : sizeof(float);
+    f->cap = lds_cap(p);
+    if (size_t(4) * f->cap * (vt + 4) <= 64 * 1024) f->wpb = 4;
+    else if (size_t(f->cap) * (vt + 4) <= kMaxLdsBytes) f->wpb = 1;
+    else {
+        kc::set_error("kc_factor_create: a row of S is too long to stage in LDS (" + std::to_string(p.max_row) +
+                      " entries)");
+        return KC_ERANGE;
+    }
     char* base = static_cast<char*>(ws_dev);
     f->n = p.n;
     f->nnz = p.nnz();
+    f->nnz_rows = p.nnz_rows();
     f->d = p.d;
     f->prec = prec;
     f->nunits = int64_t(p.units.size());
@@ -655,48 +829,44 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->rowidx = reinterpret_cast<int32_t*>(base + o.rowidx);
     f->csc2csr = reinterpret_cast<uint32_t*>(base + o.csc2csr);
     f->rowptr = reinterpret_cast<int64_t*>(base + o.rowptr);
+    f->rowend = reinterpret_cast<int64_t*>(base + o.rowend);
     f->colidx = reinterpret_cast<int32_t*>(base + o.colidx);
     f->L = base + o.L;
+    f->Lcsc = base + o.Lcsc;
     f->diag = prec == KC_MIXED ? reinterpret_cast<double*>(base + o.diag) : nullptr;
     f->units = reinterpret_cast<Unit*>(base + o.units);
     f->fwd_rows = reinterpret_cast<int32_t*>(base + o.fwd);
-    f->bwd_cols = reinterpret_cast<int32_t*>(base + o.bwd);
+    f->bwd_short = reinterpret_cast<int32_t*>(base + o.bshort);
+    f->bwd_long = reinterpret_cast<kc::LongCol*>(base + o.blong);
+    f->bwd_chunks = reinterpret_cast<kc::BwdChunk*>(base + o.bchunks);
     f->unit_off = p.unit_off;
     f->fwd_off = p.fwd_off;
+    f->short_off = bs.short_off;
+    f->long_off = bs.long_off;
+    f->chunk_off = bs.chunk_off;
+    f->max_slots = bs.max_slots;
 
-    // backward schedule: per reverse level, short columns then long columns
-    std::vector<int32_t> bwd(size_t(p.n));
-    f->bwd_beg.resize(size_t(p.nrlevels));
-    f->bwd_mid.resize(size_t(p.nrlevels));
-    f->bwd_end.resize(size_t(p.nrlevels));
-    {
-        int64_t w = 0;
-        for (int32_t v = 0; v < p.nrlevels; ++v) {
-            f->bwd_beg[v] = w;
-            for (int64_t q = p.bwd_off[v]; q < p.bwd_off[v + 1]; ++q) {
-                int32_t j = p.bwd_cols[q];
-                if (p.colptr[j + 1] - p.colptr[j] <= kLongColumn) bwd[size_t(w++)] = j;
-            }
-            f->bwd_mid[v] = w;
-            for (int64_t q = p.bwd_off[v]; q < p.bwd_off[v + 1]; ++q) {
-                int32_t j = p.bwd_cols[q];
-                if (p.colptr[j + 1] - p.colptr[j] > kLongColumn) bwd[size_t(w++)] = j;
-            }
-            f->bwd_end[v] = w;
-        }
-    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t n = size_t(p.n), nnz = size_t(p.nnz());
+    const size_t n = size_t(p.n), nnz = size_t(p.nnz()), nnzr = size_t(p.nnz_rows());
     KC_HIP(hipMemcpyAsync(f->perm, p.perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->colptr, p.colptr.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->rowidx, p.rowidx.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->csc2csr, p.csc2csr.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->rowptr, p.rowptr.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    KC_HIP(hipMemcpyAsync(f->colidx, p.colidx.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    KC_HIP(hipMemcpyAsync(f->rowend, p.rowend.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    KC_HIP(hipMemcpyAsync(f->colidx, p.colidx.data(), nnzr * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->units, p.units.data(), p.units.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->fwd_rows, p.fwd_rows.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    KC_HIP(hipMemcpyAsync(f->bwd_cols, bwd.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    // pageable sources: make sure the copies are done before the host vectors can go away
+    if (!bs.shortc.empty())
+        KC_HIP(hipMemcpyAsync(f->bwd_short, bs.shortc.data(), bs.shortc.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+    if (!bs.longc.empty())
+        KC_HIP(hipMemcpyAsync(f->bwd_long, bs.longc.data(), bs.longc.size() * sizeof(kc::LongCol),
+                              hipMemcpyHostToDevice, s));
+    if (!bs.chunks.empty())
+        KC_HIP(hipMemcpyAsync(f->bwd_chunks, bs.chunks.data(), bs.chunks.size() * sizeof(kc::BwdChunk),
+                              hipMemcpyHostToDevice, s));
+    // the sources are pageable host memory owned by the plan and bs: wait for the copies
     KC_HIP(hipStreamSynchronize(s));
     f->last = s;
     *out = f.release();
@@ -706,7 +876,7 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
 kc_status kc_factorize(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
                        int32_t count_updates, void* stream) {
     if (!f || !x_dev) return KC_EINVAL;
-    int tn = twonu_of(kernel.nu);
+    const int tn = twonu_of(kernel.nu);
     if (!tn || !(kernel.lengthscale > 0.0) || !std::isfinite(kernel.lengthscale)) {
         kc::set_error("kc_factorize: nu must be 0.5, 1.5 or 2.5 and the lengthscale finite and positive");
         return KC_EINVAL;
@@ -722,41 +892,14 @@ kc_status kc_factorize(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_p
     gather_points<<<grid_for(f->n * f->d, kBlock), kBlock, 0, s>>>(x_dev, f->perm, f->n, f->d, f->xh);
     KC_LAUNCH_CHECK();
     const bool cnt = count_updates != 0;
-    const double ell = kernel.lengthscale;
-    const int pol = int(pivot);
     const size_t nl = f->unit_off.size() - 1;
     for (size_t v = 0; v < nl; ++v) {
-        int64_t ub = f->unit_off[v], ue = f->unit_off[v + 1];
+        const int64_t ub = f->unit_off[v], ue = f->unit_off[v + 1];
         if (ue <= ub) continue;
-        dim3 grid(grid_for(ue - ub, kWavesPerBlock));
-#define KC_ICHOL_ARGS_F64                                                                                   \
-    f->units, ub, ue, f->colptr, f->rowidx, f->csc2csr, f->rowptr, f->colidx, static_cast<double*>(f->L), \
-        f->xh, f->d, ell, pol, tau, f->counters
-#define KC_ICHOL_ARGS_MIX                                                                                  \
-    f->units, ub, ue, f->colptr, f->rowidx, f->csc2csr, f->rowptr, f->colidx, static_cast<float*>(f->L), \
-        f->diag, f->xh, f->d, ell, pol, tau, f->counters
-        if (f->prec == KC_FP64) {
-            switch (tn * 2 + (cnt ? 1 : 0)) {
-                case 2: ichol_f64<1, false><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_F64); break;
-                case 3: ichol_f64<1, true><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_F64); break;
-                case 6: ichol_f64<3, false><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_F64); break;
-                case 7: ichol_f64<3, true><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_F64); break;
-                case 10: ichol_f64<5, false><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_F64); break;
-                default: ichol_f64<5, true><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_F64); break;
-            }
-        } else {
-            switch (tn * 2 + (cnt ? 1 : 0)) {
-                case 2: ichol_mixed<1, false><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_MIX); break;
-                case 3: ichol_mixed<1, true><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_MIX); break;
-                case 6: ichol_mixed<3, false><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_MIX); break;
-                case 7: ichol_mixed<3, true><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_MIX); break;
-                case 10: ichol_mixed<5, false><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_MIX); break;
-                default: ichol_mixed<5, true><<<grid, kBlock, 0, s>>>(KC_ICHOL_ARGS_MIX); break;
-            }
-        }
-#undef KC_ICHOL_ARGS_F64
-#undef KC_ICHOL_ARGS_MIX
-        KC_LAUNCH_CHECK();
+        const kc_status st = f->prec == KC_FP64
+                                 ? launch_level<double>(f, tn, cnt, ub, ue, kernel.lengthscale, int(pivot), tau, s)
+                                 : launch_level<float>(f, tn, cnt, ub, ue, kernel.lengthscale, int(pivot), tau, s);
+        if (st != KC_OK) return st;
     }
     f->factorized = true;
     f->counted = cnt;
@@ -766,7 +909,7 @@ kc_status kc_factorize(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_p
 
 kc_status kc_theta(kc_factor* f, const double* x_dev, kc_kernel kernel, double* theta_dev, void* stream) {
     if (!f || !x_dev || !theta_dev) return KC_EINVAL;
-    int tn = twonu_of(kernel.nu);
+    const int tn = twonu_of(kernel.nu);
     if (!tn || !(kernel.lengthscale > 0.0)) return KC_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     zero_u64<<<1, 64, 0, s>>>(f->counters, kNumCounters);
@@ -774,8 +917,8 @@ kc_status kc_theta(kc_factor* f, const double* x_dev, kc_kernel kernel, double* 
     gather_points<<<grid_for(f->n * f->d, kBlock), kBlock, 0, s>>>(x_dev, f->perm, f->n, f->d, f->xh);
     KC_LAUNCH_CHECK();
     if (f->nunits > 0) {
-        dim3 grid(grid_for(f->nunits, kWavesPerBlock));
-        double ell = kernel.lengthscale;
+        const dim3 grid(grid_for(f->nunits, kWavesPerBlock));
+        const double ell = kernel.lengthscale;
         if (tn == 1) theta_kernel<1><<<grid, kBlock, 0, s>>>(f->units, f->nunits, f->colptr, f->rowidx, f->xh, f->d, ell, theta_dev, f->counters);
         else if (tn == 3) theta_kernel<3><<<grid, kBlock, 0, s>>>(f->units, f->nunits, f->colptr, f->rowidx, f->xh, f->d, ell, theta_dev, f->counters);
         else theta_kernel<5><<<grid, kBlock, 0, s>>>(f->units, f->nunits, f->colptr, f->rowidx, f->xh, f->d, ell, theta_dev, f->counters);
@@ -787,10 +930,9 @@ kc_status kc_theta(kc_factor* f, const double* x_dev, kc_kernel kernel, double* 
 
 kc_status kc_solve_bytes(const kc_factor* f, int32_t nrhs, size_t* bytes) {
     if (!f || !bytes || nrhs < 1) return KC_EINVAL;
-    *bytes = size_t(f->n) * size_t(nrhs) * sizeof(double);
+    *bytes = solve_scratch_bytes(f, nrhs);
     return KC_OK;
 }
-
 
 kc_status kc_solve(const kc_factor* f, const double* b_dev, double* x_dev, int32_t nrhs, void* scratch_dev,
                    size_t scratch_bytes, void* stream) {
@@ -803,14 +945,16 @@ kc_status kc_solve(const kc_factor* f, const double* b_dev, double* x_dev, int32
         kc::set_error("kc_solve: factor has not been computed");
         return KC_ESTATE;
     }
-    if (scratch_bytes < size_t(f->n) * size_t(nrhs) * sizeof(double)) {
-        kc::set_error("kc_solve: scratch smaller than n*nrhs doubles");
+    if (scratch_bytes < solve_scratch_bytes(f, nrhs) || reinterpret_cast<uintptr_t>(scratch_dev) % 256) {
+        kc::set_error("kc_solve: scratch must be 256-byte aligned and hold kc_solve_bytes bytes");
         return KC_EWORKSPACE;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* y = static_cast<double*>(scratch_dev);
-    kc_status st = f->prec == KC_FP64 ? solve_typed<double>(f, b_dev, x_dev, nrhs, y, s)
-                                      : solve_typed<float>(f, b_dev, x_dev, nrhs, y, s);
+    double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
+                                                align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
+    const kc_status st = f->prec == KC_FP64 ? solve_typed<double>(f, b_dev, x_dev, nrhs, y, partial, s)
+                                            : solve_typed<float>(f, b_dev, x_dev, nrhs, y, partial, s);
     const_cast<kc_factor*>(f)->last = s;
     return st;
 }
@@ -833,20 +977,16 @@ kc_status kc_factor_export_L(const kc_factor* f, double* vals) {
     if (!f->factorized) return KC_ESTATE;
     KC_HIP(hipStreamSynchronize(f->last));
     const size_t nnz = size_t(f->nnz);
-    std::vector<uint32_t> c2r(nnz);
-    std::vector<int64_t> colptr(size_t(f->n) + 1);
-    KC_HIP(hipMemcpy(c2r.data(), f->csc2csr, nnz * sizeof(uint32_t), hipMemcpyDeviceToHost));
-    KC_HIP(hipMemcpy(colptr.data(), f->colptr, colptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
     if (f->prec == KC_FP64) {
-        std::vector<double> v(nnz);
-        KC_HIP(hipMemcpy(v.data(), f->L, nnz * sizeof(double), hipMemcpyDeviceToHost));
-        for (size_t e = 0; e < nnz; ++e) vals[e] = v[c2r[e]];
+        KC_HIP(hipMemcpy(vals, f->Lcsc, nnz * sizeof(double), hipMemcpyDeviceToHost));
     } else {
         std::vector<float> v(nnz);
         std::vector<double> dg(size_t(f->n));
-        KC_HIP(hipMemcpy(v.data(), f->L, nnz * sizeof(float), hipMemcpyDeviceToHost));
+        std::vector<int64_t> colptr(size_t(f->n) + 1);
+        KC_HIP(hipMemcpy(v.data(), f->Lcsc, nnz * sizeof(float), hipMemcpyDeviceToHost));
         KC_HIP(hipMemcpy(dg.data(), f->diag, dg.size() * sizeof(double), hipMemcpyDeviceToHost));
-        for (size_t e = 0; e < nnz; ++e) vals[e] = double(v[c2r[e]]);
+        KC_HIP(hipMemcpy(colptr.data(), f->colptr, colptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+        for (size_t e = 0; e < nnz; ++e) vals[e] = double(v[e]);
         for (int64_t j = 0; j < f->n; ++j) vals[colptr[size_t(j)]] = dg[size_t(j)];
     }
     return KC_OK;

@@ -15,6 +15,23 @@ struct Unit {
     int32_t first;  // offset of the chunk's first entry inside column j
 };
 
+constexpr int kRowAlign = 16;
+
+// Backward solve of a long column: one piece of its dot product ...
+struct BwdChunk {
+    int32_t col;    // column j
+    int32_t start;  // first off-diagonal entry of the piece, counted from the diagonal's successor
+    int32_t slot;   // where the piece's partial sums go (per reverse level)
+    int32_t pad;
+};
+// ... and the column that combines its pieces' partial sums.
+struct LongCol {
+    int32_t col;
+    int32_t slot0;
+    int32_t nslots;
+    int32_t pad;
+};
+
 struct Plan {
     int64_t n = 0;
     int32_t d = 0;
@@ -28,8 +45,10 @@ struct Plan {
     // lower triangle of S incl. diagonal, CSC (rows ascending, diagonal first)
     std::vector<int64_t> colptr;
     std::vector<int32_t> rowidx;
-    // the same entries by rows (CSR, columns ascending, diagonal last)
-    std::vector<int64_t> rowptr;
+    // the same entries by rows (CSR, columns ascending, diagonal last); each row
+    // starts on a multiple of kRowAlign entries and is padded with INT32_MAX
+    std::vector<int64_t> rowptr;    // n + 1 padded row starts
+    std::vector<int64_t> rowend;    // n: one past the diagonal
     std::vector<int32_t> colidx;
     std::vector<uint32_t> csc2csr;  // CSR position of each CSC entry
 
@@ -49,6 +68,7 @@ struct Plan {
     double t_order = 0, t_pattern = 0, t_schedule = 0;
 
     int64_t nnz() const { return colptr.empty() ? 0 : colptr.back(); }
+    int64_t nnz_rows() const { return rowptr.empty() ? 0 : rowptr.back(); }  // padded
 };
 
 // analysis.cpp
