@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--cpu-grid", type=int, default=250, help="m of the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -120,6 +122,16 @@ def main():
     info = plan.info()
     log(f"[bench] host analysis {t_analysis:.2f} s: nnz={info['nnz']} levels={info['nlevels']} "
         f"units={info['nunits']}")
+
+    if args.copy_mib > 0:
+        import torch
+        src = torch.ones(args.copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {args.copy_mib} MiB device-to-device")
+        del src, dst
 
     pivot, tau = ("zero", 0.0) if args.prec == "fp64" else ("shift", 1e-6)
     r = run_gpu(w, args.prec, args.steps, args.warmup, plan, pivot, tau)

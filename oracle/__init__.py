@@ -58,8 +58,14 @@ def lib():
         L.or_llt_pairs.argtypes = [I64, _i64p, _i32p, _f64p, I64, _i64p, _i64p, _f64p]
         L.or_frob_error.argtypes = [_f64p, I64, I32, F64, F64, _i64p, _i32p, _f64p, _f64p]
         L.or_num_threads.argtypes = []
+        L.or_prefix_min_dist.argtypes = [_f64p, I32, I64, _i64p, _f64p]
+        L.or_pattern_column.argtypes = [_f64p, I64, I32, _f64p, F64, I32, I64, _i32p]
+        L.or_pattern_column.restype = C.c_int64
+        L.or_theta_pairs.argtypes = [_f64p, I32, F64, F64, I64, _i64p, _i64p, _f64p]
+        L.or_ichol_leading.argtypes = [I64, _i64p, _i32p, I64, _f64p, I32, F64, _f64p]
         for fn in ("or_maximin", "or_pattern_count", "or_pattern_fill", "or_matern", "or_theta", "or_ichol",
-                   "or_solve", "or_llt_pairs", "or_frob_error", "or_num_threads"):
+                   "or_solve", "or_llt_pairs", "or_frob_error", "or_num_threads", "or_prefix_min_dist",
+                   "or_theta_pairs", "or_ichol_leading"):
             getattr(L, fn).restype = C.c_int
         _LIB = L
     return _LIB
@@ -217,3 +223,47 @@ def dense_from_csc(P: Pattern, vals: np.ndarray) -> np.ndarray:
     cols = np.repeat(np.arange(n), np.diff(P.colptr))
     M[P.rowidx, cols] = vals
     return M
+
+
+# --------------------------------------------------------------------------
+# One-by-one checks for samples of problems too large for the O(N^2) oracle.
+
+def prefix_min_dist(xh: np.ndarray, ks: np.ndarray) -> np.ndarray:
+    """min_{i<k} dist(xh_k, xh_i) for each k in ks: l[k] of the maximin ordering (Section 2.3)."""
+    xh = np.ascontiguousarray(xh, dtype=np.float64)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    out = np.empty(ks.size, np.float64)
+    _check(lib().or_prefix_min_dist(xh, xh.shape[1], ks.size, ks, out), "prefix_min_dist")
+    return out
+
+
+def pattern_column(xh: np.ndarray, l: np.ndarray, rho: float, b: int, rule: int = RULE_MAX) -> np.ndarray:
+    """Rows of column b of S_rho (Section 2.3), brute force over all later points."""
+    xh = np.ascontiguousarray(xh, dtype=np.float64)
+    n, d = xh.shape
+    rows = np.empty(n - b, np.int32)
+    c = lib().or_pattern_column(xh, n, d, np.ascontiguousarray(l, dtype=np.float64), float(rho), int(rule), int(b),
+                                rows)
+    return rows[:c]
+
+
+def theta_pairs(xh: np.ndarray, nu: float, ell: float, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Theta_ab (Section 4.4 Matern) for pairs of ordered points."""
+    xh = np.ascontiguousarray(xh, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    b = np.ascontiguousarray(b, dtype=np.int64)
+    out = np.empty(a.size, np.float64)
+    _check(lib().or_theta_pairs(xh, xh.shape[1], float(nu), float(ell), a.size, a, b, out), "theta_pairs")
+    return out
+
+
+def ichol_leading(colptr: np.ndarray, rowidx: np.ndarray, m: int, theta_lead: np.ndarray,
+                  policy: int = PIVOT_ZERO, tau: float = 0.0) -> np.ndarray:
+    """The first m columns of ICHOL(0) (Section 2.2) in the same per-entry order as :func:`ichol`."""
+    n = colptr.size - 1
+    L = np.empty(int(colptr[m]), np.float64)
+    _check(lib().or_ichol_leading(n, np.ascontiguousarray(colptr, dtype=np.int64),
+                                  np.ascontiguousarray(rowidx, dtype=np.int32), int(m),
+                                  np.ascontiguousarray(theta_lead, dtype=np.float64), int(policy), float(tau), L),
+           "ichol_leading")
+    return L

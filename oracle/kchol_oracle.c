@@ -358,3 +358,90 @@ int or_frob_error(const double *xh, int64_t n, int32_t d, double nu, double ell,
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------ */
+/* One-by-one versions of the definitions above, for checking samples of a
+ * large problem.  xh, l and the pattern are those under test. */
+
+/* out[t] = min_{i < k_t} dist(xh_{k_t}, xh_i): l[k] of the maximin ordering (Section 2.3). */
+int or_prefix_min_dist(const double *xh, int32_t d, int64_t m, const int64_t *ks, double *out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < m; ++t) {
+        int64_t k = ks[t];
+        double best = INFINITY;
+        for (int64_t i = 0; i < k; ++i) {
+            double r = dist(xh + (size_t)k * d, xh + (size_t)i * d, d);
+            if (r < best) best = r;
+        }
+        out[t] = best;
+    }
+    return OR_OK;
+}
+
+/* Rows of column b of S (Section 2.3), ascending, diagonal first; returns the count
+ * (rows must hold n - b entries). */
+int64_t or_pattern_column(const double *xh, int64_t n, int32_t d, const double *l, double rho, int32_t rule,
+                          int64_t b, int32_t *rows) {
+    int64_t c = 0;
+    for (int64_t a = b; a < n; ++a)
+        if (in_pattern(xh, d, l, rho, rule, a, b)) rows[c++] = (int32_t)a;
+    return c;
+}
+
+/* Theta_{a_t b_t} (Section 4.4 Matern) for index pairs of the ordered points. */
+int or_theta_pairs(const double *xh, int32_t d, double nu, double ell, int64_t m, const int64_t *a,
+                   const int64_t *b, double *out) {
+    int tn = twonu_of(nu);
+    if (!tn || !(ell > 0.0)) return OR_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < m; ++t)
+        out[t] = matern(dist(xh + (size_t)a[t] * d, xh + (size_t)b[t] * d, d), tn, ell);
+    return OR_OK;
+}
+
+/* The first m columns of ICHOL(0) (Section 2.2).  Entries of column j < m are
+ * final once columns 0..j-1 have been eliminated, so they can be computed on
+ * their own: A_kj = Theta_kj, then for i = 0..j-1 with (j,i),(k,i) in S,
+ * ascending, A_kj = fma(-L_ki, L_ji, A_kj) -- the per-entry order of the
+ * right-looking algorithm -- followed by the pivot rule and the division.
+ * colptr/rowidx: the pattern (CSC); theta: Theta on the first m columns in
+ * CSC order (colptr[m] entries); L: output, same layout. */
+int or_ichol_leading(int64_t n, const int64_t *colptr, const int32_t *rowidx, int64_t m, const double *theta,
+                     int32_t policy, double tau, double *L) {
+    if (m < 0 || m > n) return OR_EINVAL;
+    int64_t *map = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!map) return OR_ENOMEM;
+    for (int64_t k = 0; k < n; ++k) map[k] = -1;
+    memcpy(L, theta, (size_t)colptr[m] * sizeof(double));
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t c0 = colptr[j], c1 = colptr[j + 1];
+        for (int64_t e = c0; e < c1; ++e) map[rowidx[e]] = e;
+        for (int64_t i = 0; i < j; ++i) {
+            int64_t ij = -1; /* position of (j, i) in column i */
+            for (int64_t f = colptr[i]; f < colptr[i + 1]; ++f)
+                if (rowidx[f] == j) { ij = f; break; }
+            if (ij < 0 || L[colptr[i]] == 0.0) continue; /* not a parent, or a zeroed column */
+            double lji = L[ij];
+            for (int64_t f = ij; f < colptr[i + 1]; ++f) {
+                int64_t g = map[rowidx[f]];
+                if (g >= 0) L[g] = fma(-L[f], lji, L[g]);
+            }
+        }
+        for (int64_t e = c0; e < c1; ++e) map[rowidx[e]] = -1;
+        double p = L[c0];
+        if (policy == OR_PIVOT_ZERO) {
+            if (!(p > 0.0)) {
+                for (int64_t e = c0; e < c1; ++e) L[e] = 0.0;
+                continue;
+            }
+        } else {
+            double floor_ = tau * theta[c0];
+            if (!(p > floor_)) p = floor_;
+        }
+        double s = sqrt(p);
+        L[c0] = s;
+        for (int64_t e = c0 + 1; e < c1; ++e) L[e] = L[e] / s;
+    }
+    free(map);
+    return OR_OK;
+}

@@ -390,7 +390,8 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     }
 }
 
-// Completes the long columns of a reverse level from their partial sums (fixed order).
+// Completes the long columns of a reverse level from their partial sums: one
+// wavefront per column, lanes take every 64th piece, then a fixed butterfly.
 template <typename VT, int NR>
 __global__ __launch_bounds__(kBlock) void bwd_combine(const kc::LongCol* __restrict__ lcols, int64_t beg,
                                                       int64_t end, const int64_t* __restrict__ colptr,
@@ -398,18 +399,33 @@ __global__ __launch_bounds__(kBlock) void bwd_combine(const kc::LongCol* __restr
                                                       const int32_t* __restrict__ perm, int ld, int r0,
                                                       const double* __restrict__ partial, double* __restrict__ y,
                                                       double* __restrict__ x) {
-    const int64_t t = beg + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
     if (t >= end) return;
     const kc::LongCol lc = lcols[t];
-    const double ljj = diag_value(Lcsc, diag, colptr[lc.col], lc.col);
+    double s[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        double s = 0.0;
-        for (int q = 0; q < lc.nslots; ++q) s += partial[int64_t(lc.slot0 + q) * NR + r];
-        double* yj = y + int64_t(lc.col) * ld + r0 + r;
-        const double v = (ljj == 0.0) ? 0.0 : (*yj - s) / ljj;
-        *yj = v;
-        x[int64_t(perm[lc.col]) * ld + r0 + r] = v;
+    for (int r = 0; r < NR; ++r) s[r] = 0.0;
+    for (int q = lane; q < lc.nslots; q += kWave) {
+        const double* pq = partial + int64_t(lc.slot0 + q) * NR;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s[r] += pq[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s[r] += __shfl_xor(s[r], off, kWave);
+    if (lane < NR) {
+        double v = s[0];
+#pragma unroll
+        for (int r = 1; r < NR; ++r)
+            if (lane == r) v = s[r];
+        const double ljj = diag_value(Lcsc, diag, colptr[lc.col], lc.col);
+        double* yj = y + int64_t(lc.col) * ld + r0 + lane;
+        const double xv = (ljj == 0.0) ? 0.0 : (*yj - v) / ljj;
+        *yj = xv;
+        x[int64_t(perm[lc.col]) * ld + r0 + lane] = xv;
     }
 }
 
@@ -620,7 +636,7 @@ kc_status solve_pass(const kc_factor* f, const double* b, double* x, int ld, int
                 f->bwd_chunks, cb, ce, f->colptr, f->rowidx, Lc, ld, r0, y, partial);
             KC_LAUNCH_CHECK();
             const int64_t lb = f->long_off[v], le = f->long_off[v + 1];
-            bwd_combine<VT, NR><<<grid_for(le - lb, kBlock), kBlock, 0, s>>>(f->bwd_long, lb, le, f->colptr, Lc,
+            bwd_combine<VT, NR><<<grid_for(le - lb, kWavesPerBlock), kBlock, 0, s>>>(f->bwd_long, lb, le, f->colptr, Lc,
                                                                             f->diag, f->perm, ld, r0, partial, y, x);
             KC_LAUNCH_CHECK();
         }

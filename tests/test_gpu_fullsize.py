@@ -1,0 +1,89 @@
+"""GPU parity at the benchmark's full size: 10^6 points on a jittered 1000x1000 grid,
+Matern nu=1/2, l=0.1, rho=4, 8 right-hand sides, in the launch configuration the
+benchmark times.  The O(N^2) oracle cannot run at this size, so the oracle checks
+samples one by one and properties that hold at any size:
+
+* l[k] of sampled positions equals the distance to the points ordered before them;
+* sampled columns of S equal the brute-force column;
+* Theta on sampled entries is bitwise the oracle's;
+* the leading 16 columns of L (the dense top of the factor, ~1.6e7 entries) are
+  bitwise the oracle's, computed in the same per-entry order;
+* (L L^T)_ab = Theta_ab on sampled entries of S (the defining IC(0) identity),
+  to 1e-12 relative to Theta_aa = 1;
+* the solve's componentwise backward error |Pb - L L^T x| <= 1e-10 |L| |L^T| |x|.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from paper_1706_02205_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1706_02205_amd as K
+    w = W.large_grid_2d(1000)
+    print("[gpu] full size: analysis", flush=True)
+    plan = K.analyze(w.points, w.rho)
+    perm, l, colptr, rowidx = plan.export()
+    print(f"[gpu] full size: factorize nnz={colptr[-1]}", flush=True)
+    f = K.Factor(plan, "fp64")
+    xd = torch.from_numpy(w.points).to("cuda")
+    f.factorize(xd, w.nu, w.lengthscale)
+    b = w.rhs()
+    x = f.solve(torch.from_numpy(b).to("cuda")).cpu().numpy()
+    st = f.stats()
+    L = f.export_L()
+    print("[gpu] full size: factor exported", flush=True)
+    return dict(w=w, perm=perm, l=l, colptr=colptr, rowidx=rowidx, xh=np.ascontiguousarray(w.points[perm]),
+                L=L, b=b, x=x, st=st)
+
+
+def test_ordering_and_pattern_samples(big):
+    rng = np.random.default_rng(0)
+    n = big["l"].size
+    ks = np.concatenate([np.arange(1, 40), rng.integers(40, n, 60)])
+    assert np.array_equal(O.prefix_min_dist(big["xh"], ks), big["l"][ks])
+    assert np.all(np.diff(big["l"][1:]) <= 0)
+    for b in np.concatenate([np.arange(0, 5), rng.integers(5, n, 40)]):
+        got = big["rowidx"][big["colptr"][b]:big["colptr"][b + 1]]
+        assert np.array_equal(O.pattern_column(big["xh"], big["l"], big["w"].rho, int(b)), got)
+
+
+def test_leading_columns_bitwise(big):
+    m = 16
+    cp, ri = big["colptr"], big["rowidx"]
+    cols = np.repeat(np.arange(m, dtype=np.int64), np.diff(cp[:m + 1]))
+    th = O.theta_pairs(big["xh"], big["w"].nu, big["w"].lengthscale, ri[:cp[m]].astype(np.int64), cols)
+    ref = O.ichol_leading(cp, ri, m, th)
+    assert np.array_equal(big["L"][:cp[m]], ref)
+    assert big["st"].exp_hard == 0 and big["st"].nonpositive == 0
+
+
+def test_ic0_identity_on_sampled_entries(big):
+    rng = np.random.default_rng(1)
+    cp, ri = big["colptr"], big["rowidx"]
+    e = rng.integers(0, cp[-1], 200_000)
+    a = ri[e].astype(np.int64)
+    b = (np.searchsorted(cp, e, side="right") - 1).astype(np.int64)
+    th = O.theta_pairs(big["xh"], big["w"].nu, big["w"].lengthscale, a, b)
+    P = O.Pattern(big["perm"], big["l"], cp, ri, big["xh"])
+    llt = O.llt_pairs(P, big["L"], a, b)
+    assert np.max(np.abs(llt - th)) < 1e-12
+
+
+def test_solve_backward_error(big):
+    n = big["l"].size
+    Lm = sp.csc_matrix((big["L"], big["rowidx"], big["colptr"]), shape=(n, n))
+    Labs = abs(Lm)
+    xh = big["x"][big["perm"]]
+    bh = big["b"][big["perm"]]
+    resid = np.abs(bh - Lm @ (Lm.T @ xh))
+    scale = Labs @ (Labs.T @ np.abs(xh))
+    assert np.max(resid / scale) < 1e-10
