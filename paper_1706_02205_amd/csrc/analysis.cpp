@@ -284,6 +284,7 @@ void build_pattern(Plan& p, int nthreads) {
     const double* xh = p.xh.data();
     KDTree tree;
     tree.build(xh, n, d);
+    p.spatial = tree.idx;  // k-d tree leaf order: positions grouped by region
     std::vector<int64_t> cnt(size_t(n), 0);
 
     if (p.rule == KC_RULE_MAX) {
@@ -395,7 +396,10 @@ void build_schedule(Plan& p, int nthreads) {
     p.units.resize(size_t(uoff[nl]));
     {
         std::vector<int64_t> lf(loff.begin(), loff.end() - 1), uf(uoff.begin(), uoff.end() - 1);
-        for (int64_t j = 0; j < n; ++j) {
+        // within a level, columns follow the k-d tree leaf order, so that
+        // consecutive work units touch nearby points and the same rows of L
+        for (int64_t t = 0; t < n; ++t) {
+            const int32_t j = p.spatial[size_t(t)];
             int32_t v = p.level[j];
             p.fwd_rows[size_t(lf[v]++)] = int32_t(j);
             int64_t len = p.colptr[j + 1] - p.colptr[j];

@@ -133,6 +133,18 @@ struct RowWindow {
     }
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// Renumber them so that each XCD receives one contiguous range of blocks: the
+// units of a level are laid out in spatial order, so each XCD's L2 then serves
+// one region of the point cloud.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block() {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int q = nb / kNumXcd, r = nb % kNumXcd;
+    const int x = b % kNumXcd, i = b / kNumXcd;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // ---------------------------------------------------------------------------
 // A1+A2: Theta on S fused into ICHOL(0), one DAG level per launch.
 //
@@ -167,7 +179,7 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(
     VT* sval = reinterpret_cast<VT*>(smem) + wave * cap;
     int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(WPB) * cap * sizeof(VT)) + wave * cap;
 
-    const int64_t u = ubeg + int64_t(blockIdx.x) * WPB + wave;
+    const int64_t u = ubeg + int64_t(xcd_block()) * WPB + wave;
     const bool valid = u < uend;
     int j = 0, first = 0, np = 0;
     int64_t t0 = 0;

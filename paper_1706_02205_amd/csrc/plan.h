@@ -41,6 +41,7 @@ struct Plan {
     std::vector<int32_t> perm;      // maximin position -> original index
     std::vector<double> l;          // l[k], l[0] = +inf
     std::vector<double> xh;         // points in maximin order, n x d
+    std::vector<int32_t> spatial;   // positions in k-d tree leaf order (a spatial order for any d)
 
     // lower triangle of S incl. diagonal, CSC (rows ascending, diagonal first)
     std::vector<int64_t> colptr;
