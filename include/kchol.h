@@ -157,6 +157,35 @@ kc_status kc_factor_export_L(const kc_factor *f, double *vals);
 
 void kc_factor_destroy(kc_factor *f);
 
+/* ---------------------------------------------------------------- refinement */
+
+typedef struct {
+    int32_t iterations;        /* CG iterations performed */
+    int32_t converged;         /* 1 when every right-hand side reached tol */
+    double max_rel_residual;   /* max over right-hand sides of ||r||/||b|| (recursive residual) */
+    double t_matvec_ms;        /* time in dense Theta products */
+    double t_precond_ms;       /* time in the preconditioner solves */
+} kc_pcg_info_t;
+
+/* Y = Theta X with the dense N x N Matern matrix (Section 4.4) generated on the
+ * fly: x_dev N x d (d <= 32) points, X_dev/Y_dev N x nrhs row-major, all in the
+ * same (any) order.  FP64; X and Y may not alias. */
+kc_status kc_dense_matvec(const double *x_dev, int64_t n, int32_t d, kc_kernel kernel, const double *X_dev,
+                          double *Y_dev, int32_t nrhs, void *stream);
+
+/* Scratch needed by kc_pcg. */
+kc_status kc_pcg_bytes(const kc_factor *f, int32_t nrhs, size_t *bytes);
+
+/* Conjugate gradients on the dense system Theta x = b preconditioned by the
+ * factor, M^{-1} = P^T L^{-T} L^{-1} P (the paper suggests CG with the sparse
+ * factor as preconditioner, Sections 4.2-4.3).  x0 = 0; each right-hand side
+ * stops when ||r||/||b|| <= tol (FP64 residuals).  b_dev, sol_dev: N x nrhs in
+ * the original order; x_dev: the points the factor was computed from.  Blocks
+ * the host once per iteration for the convergence test. */
+kc_status kc_pcg(kc_factor *f, const double *x_dev, kc_kernel kernel, const double *b_dev, double *sol_dev,
+                 int32_t nrhs, double tol, int32_t maxit, void *scratch_dev, size_t scratch_bytes, void *stream,
+                 kc_pcg_info_t *info);
+
 /* Number of HIP devices visible (0 if none); for availability checks. */
 int32_t kc_device_count(void);
 

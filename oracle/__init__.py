@@ -63,9 +63,11 @@ def lib():
         L.or_pattern_column.restype = C.c_int64
         L.or_theta_pairs.argtypes = [_f64p, I32, F64, F64, I64, _i64p, _i64p, _f64p]
         L.or_ichol_leading.argtypes = [I64, _i64p, _i32p, I64, _f64p, I32, F64, _f64p]
+        L.or_dense_matvec.argtypes = [_f64p, I64, I32, F64, F64, _f64p, I32, _f64p]
+        L.or_dense_matvec_rows.argtypes = [_f64p, I64, I32, F64, F64, _f64p, I32, I64, _i64p, _f64p]
         for fn in ("or_maximin", "or_pattern_count", "or_pattern_fill", "or_matern", "or_theta", "or_ichol",
                    "or_solve", "or_llt_pairs", "or_frob_error", "or_num_threads", "or_prefix_min_dist",
-                   "or_theta_pairs", "or_ichol_leading"):
+                   "or_theta_pairs", "or_ichol_leading", "or_dense_matvec", "or_dense_matvec_rows"):
             getattr(L, fn).restype = C.c_int
         _LIB = L
     return _LIB
@@ -267,3 +269,54 @@ def ichol_leading(colptr: np.ndarray, rowidx: np.ndarray, m: int, theta_lead: np
                                   np.ascontiguousarray(theta_lead, dtype=np.float64), int(policy), float(tau), L),
            "ichol_leading")
     return L
+
+
+# --------------------------------------------------------------------------
+# Conjugate gradients with the sparse factor as preconditioner (Sections 4.2-4.3).
+
+def dense_matvec(x: np.ndarray, X: np.ndarray, nu: float, ell: float) -> np.ndarray:
+    """Theta X with the dense Matern matrix of the points x (any order)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    X2 = np.ascontiguousarray(X[:, None] if X.ndim == 1 else X, dtype=np.float64)
+    Y = np.empty_like(X2)
+    _check(lib().or_dense_matvec(x, x.shape[0], x.shape[1], float(nu), float(ell), X2, X2.shape[1], Y), "dense_matvec")
+    return Y[:, 0] if X.ndim == 1 else Y
+
+
+def dense_matvec_rows(x: np.ndarray, X: np.ndarray, nu: float, ell: float, rows: np.ndarray) -> np.ndarray:
+    """Rows `rows` of Theta X."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    X2 = np.ascontiguousarray(X[:, None] if X.ndim == 1 else X, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    Y = np.empty((rows.size, X2.shape[1]), np.float64)
+    _check(lib().or_dense_matvec_rows(x, x.shape[0], x.shape[1], float(nu), float(ell), X2, X2.shape[1], rows.size,
+                                      rows, Y), "dense_matvec_rows")
+    return Y
+
+
+def pcg(P: Pattern, L: np.ndarray, x: np.ndarray, nu: float, ell: float, b: np.ndarray, tol: float = 1e-10,
+        maxit: int = 200):
+    """Textbook preconditioned CG on Theta sol = b, x0 = 0, M^-1 = P^T L^-T L^-1 P, every
+    right-hand side stopped once ||r||/||b|| <= tol.  Returns (sol, iterations)."""
+    b2 = b[:, None] if b.ndim == 1 else b
+    sol = np.zeros_like(b2)
+    r = b2.copy()
+    nb = np.linalg.norm(b2, axis=0)
+    z = solve(P, L, r)
+    p = z.copy()
+    rz = (r * z).sum(axis=0)
+    active = np.ones(b2.shape[1], bool)
+    it = 0
+    for it in range(1, maxit + 1):
+        q = dense_matvec(x, p, nu, ell)
+        alpha = np.where(active, rz / (p * q).sum(axis=0), 0.0)
+        sol += alpha * p
+        r -= alpha * q
+        active &= np.linalg.norm(r, axis=0) / nb > tol
+        if not active.any():
+            break
+        z = solve(P, L, r)
+        rz_new = (r * z).sum(axis=0)
+        p = np.where(active, z + (rz_new / rz) * p, p)
+        rz = rz_new
+    return (sol[:, 0] if b.ndim == 1 else sol), it

@@ -445,3 +445,39 @@ int or_ichol_leading(int64_t n, const int64_t *colptr, const int32_t *rowidx, in
     free(map);
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Y = Theta X with the dense Matern matrix (Section 4.4), j ascending; X, Y n x nrhs.
+ * Used by the conjugate-gradient reference (Sections 4.2-4.3: CG with the sparse
+ * factor as preconditioner). */
+int or_dense_matvec(const double *x, int64_t n, int32_t d, double nu, double ell, const double *X, int32_t nrhs,
+                    double *Y) {
+    int tn = twonu_of(nu);
+    if (!tn || !(ell > 0.0)) return OR_EINVAL;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t r = 0; r < nrhs; ++r) Y[i * nrhs + r] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double th = matern(dist(x + (size_t)i * d, x + (size_t)j * d, d), tn, ell);
+            for (int32_t r = 0; r < nrhs; ++r) Y[i * nrhs + r] += th * X[j * nrhs + r];
+        }
+    }
+    return OR_OK;
+}
+
+/* Rows ks of Theta X only (for sampled residuals of large problems). */
+int or_dense_matvec_rows(const double *x, int64_t n, int32_t d, double nu, double ell, const double *X,
+                         int32_t nrhs, int64_t m, const int64_t *ks, double *Y) {
+    int tn = twonu_of(nu);
+    if (!tn || !(ell > 0.0)) return OR_EINVAL;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < m; ++t) {
+        int64_t i = ks[t];
+        for (int32_t r = 0; r < nrhs; ++r) Y[t * nrhs + r] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double th = matern(dist(x + (size_t)i * d, x + (size_t)j * d, d), tn, ell);
+            for (int32_t r = 0; r < nrhs; ++r) Y[t * nrhs + r] += th * X[j * nrhs + r];
+        }
+    }
+    return OR_OK;
+}

@@ -20,7 +20,7 @@ import numpy as np
 from . import _lib
 from ._lib import KCholError
 
-__all__ = ["analyze", "Plan", "Factor", "KCholError"]
+__all__ = ["analyze", "dense_matvec", "Plan", "Factor", "KCholError"]
 
 _RULES = {"max": _lib.KC_RULE_MAX, "min": _lib.KC_RULE_MIN}
 _PRECS = {"fp64": _lib.KC_FP64, "mixed": _lib.KC_MIXED}
@@ -40,8 +40,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            _lib.load().kc_plan_destroy(h)
+        if h and _lib is not None and _lib._LIB is not None:
+            _lib._LIB.kc_plan_destroy(h)
             self._h = None
 
     @property
@@ -92,6 +92,30 @@ def _stream_ptr(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def dense_matvec(x_dev, X_dev, nu: float, lengthscale: float, stream=None):
+    """Y = Theta X with the dense Matern matrix of the points x_dev (N x d), generated on the fly."""
+    import torch
+    for t in (x_dev, X_dev):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("points and X must be contiguous float64 CUDA tensors")
+    n, d = x_dev.shape
+    nrhs = 1 if X_dev.dim() == 1 else int(X_dev.shape[1])
+    Y = torch.empty_like(X_dev)
+    _lib.check(_lib.load().kc_dense_matvec(C.c_void_p(x_dev.data_ptr()), n, d, _lib.kc_kernel(nu, lengthscale),
+                                           C.c_void_p(X_dev.data_ptr()), C.c_void_p(Y.data_ptr()), nrhs,
+                                           _stream_ptr(stream)), "kc_dense_matvec")
+    return Y
+
+
+@dataclass
+class PcgInfo:
+    iterations: int
+    converged: bool
+    max_rel_residual: float
+    t_matvec_ms: float
+    t_precond_ms: float
+
+
 @dataclass
 class Stats:
     nonpositive: int
@@ -119,8 +143,8 @@ class Factor:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            _lib.load().kc_factor_destroy(h)
+        if h and _lib is not None and _lib._LIB is not None:
+            _lib._LIB.kc_factor_destroy(h)
             self._h = None
 
     @property
@@ -162,6 +186,25 @@ class Factor:
                                         C.c_void_p(self._scratch.data_ptr()), self._scratch.numel(),
                                         _stream_ptr(stream)), "kc_solve")
         return x
+
+    def pcg(self, x_dev, b_dev, nu: float, lengthscale: float, tol: float = 1e-10, maxit: int = 200, stream=None):
+        """Solve Theta x = b by CG on the dense Theta preconditioned with this factor."""
+        import torch
+        if b_dev.dtype != torch.float64 or not b_dev.is_cuda or not b_dev.is_contiguous():
+            raise ValueError("b must be a contiguous float64 CUDA tensor")
+        self._check_points(x_dev)
+        nrhs = 1 if b_dev.dim() == 1 else int(b_dev.shape[1])
+        nb = C.c_size_t()
+        _lib.check(_lib.load().kc_pcg_bytes(self._h, nrhs, C.byref(nb)), "kc_pcg_bytes")
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=b_dev.device)
+        sol = torch.empty_like(b_dev)
+        info = _lib.kc_pcg_info_t()
+        _lib.check(_lib.load().kc_pcg(self._h, C.c_void_p(x_dev.data_ptr()), _lib.kc_kernel(nu, lengthscale),
+                                      C.c_void_p(b_dev.data_ptr()), C.c_void_p(sol.data_ptr()), nrhs, float(tol),
+                                      int(maxit), C.c_void_p(scratch.data_ptr()), scratch.numel(),
+                                      _stream_ptr(stream), C.byref(info)), "kc_pcg")
+        return sol, PcgInfo(info.iterations, bool(info.converged), info.max_rel_residual, info.t_matvec_ms,
+                            info.t_precond_ms)
 
     def stats(self) -> Stats:
         st = _lib.kc_factor_stats_t()

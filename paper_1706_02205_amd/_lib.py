@@ -24,6 +24,11 @@ class kc_plan_info_t(C.Structure):
                 ("t_order_s", C.c_double), ("t_pattern_s", C.c_double), ("t_schedule_s", C.c_double)]
 
 
+class kc_pcg_info_t(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("max_rel_residual", C.c_double),
+                ("t_matvec_ms", C.c_double), ("t_precond_ms", C.c_double)]
+
+
 class kc_factor_stats_t(C.Structure):
     _fields_ = [("nonpositive", C.c_int64), ("shifted", C.c_int64), ("rank", C.c_int64),
                 ("updates", C.c_int64), ("exp_hard", C.c_int64)]
@@ -31,7 +36,8 @@ class kc_factor_stats_t(C.Structure):
 
 EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "kc_plan_export", "kc_plan_levels",
             "kc_plan_destroy", "kc_factor_bytes", "kc_factor_create", "kc_factorize", "kc_theta", "kc_solve_bytes",
-            "kc_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count")
+            "kc_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
+            "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg")
 
 _LIB = None
 
@@ -72,6 +78,9 @@ def load():
         "kc_factor_export_L": (C.c_int, [vp, vp]),
         "kc_factor_destroy": (None, [vp]),
         "kc_device_count": (i32, []),
+        "kc_dense_matvec": (C.c_int, [vp, i64, i32, kc_kernel, vp, vp, i32, vp]),
+        "kc_pcg_bytes": (C.c_int, [vp, i32, P(sz)]),
+        "kc_pcg": (C.c_int, [vp, vp, kc_kernel, vp, vp, i32, f64, i32, vp, sz, vp, P(kc_pcg_info_t)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", *HOST_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    for src in ("kchol.hip",):
+    for src in ("kchol.hip", "pcg.hip"):
         obj = os.path.join(BUILD, src + ".o")
         _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

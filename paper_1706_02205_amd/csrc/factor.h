@@ -1,0 +1,42 @@
+// Device-side state of one factor (shared by the factorization, solve and PCG sources).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "kchol.h"
+#include "plan.h"
+
+struct kc_factor {
+    int64_t n = 0, nnz = 0, nnz_rows = 0, nunits = 0;
+    int32_t d = 0;
+    int32_t cap = 0;          // LDS entries per wavefront (longest row, rounded up)
+    int32_t wpb = 4;          // wavefronts per block of the factorization kernel
+    kc_prec prec = KC_FP64;
+    // device regions
+    unsigned long long* counters = nullptr;
+    double* xh = nullptr;
+    int32_t* perm = nullptr;
+    int64_t* colptr = nullptr;
+    int32_t* rowidx = nullptr;
+    uint32_t* csc2csr = nullptr;
+    int64_t* rowptr = nullptr;
+    int64_t* rowend = nullptr;
+    int32_t* colidx = nullptr;
+    void* L = nullptr;        // by rows: double[nnz_rows] or float[nnz_rows]
+    void* Lcsc = nullptr;     // by columns: double[nnz] or float[nnz]
+    double* diag = nullptr;   // MIXED only
+    kc::Unit* units = nullptr;
+    int32_t* fwd_rows = nullptr;
+    int32_t* bwd_short = nullptr;
+    kc::LongCol* bwd_long = nullptr;
+    kc::BwdChunk* bwd_chunks = nullptr;
+    // host schedule
+    std::vector<int64_t> unit_off, fwd_off, short_off, long_off, chunk_off;
+    int64_t max_slots = 0;    // partial sums needed by the widest reverse level
+    bool factorized = false;
+    bool counted = false;
+    hipStream_t last = nullptr;
+};
