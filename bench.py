@@ -67,7 +67,7 @@ def algorithmic_bytes(prec, nnz, updates):
     return 8 * nnz + 8 * updates
 
 
-def run_gpu(w, prec, steps, warmup, plan, pivot, tau):
+def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol):
     import torch
     import paper_1706_02205_amd as K
     torch.cuda.synchronize()
@@ -99,9 +99,24 @@ def run_gpu(w, prec, steps, warmup, plan, pivot, tau):
     t_fac = np.array([a.elapsed_time(b) for a, b, _ in ev]) / 1e3
     t_sol = np.array([b.elapsed_time(c) for _, b, c in ev]) / 1e3
     st2 = f.stats()
+    refine = None
+    if pcg_tol > 0:
+        # time to a pcg_tol residual: factorization + CG on the dense Theta preconditioned by it
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        f.factorize(xd, w.nu, w.lengthscale, pivot, tau)
+        sol, info = f.pcg(xd, bd, w.nu, w.lengthscale, tol=pcg_tol, maxit=200)
+        b.record()
+        torch.cuda.synchronize()
+        n2 = float(w.n) ** 2
+        refine = {"tol": pcg_tol, "seconds_to_tol": a.elapsed_time(b) / 1e3, "iterations": info.iterations,
+                  "converged": info.converged, "max_rel_residual": info.max_rel_residual,
+                  "dense_matvec_s": info.t_matvec_ms / 1e3, "precond_s": info.t_precond_ms / 1e3,
+                  "dense_pairs_per_s": n2 * info.iterations / (info.t_matvec_ms / 1e3)}
     return dict(wall=wall, t_factor=t_fac, t_solve=t_sol, updates=st.updates, rank=st2.rank,
                 nonpositive=st2.nonpositive, shifted=st2.shifted, exp_hard=st2.exp_hard, t_upload=t_upload,
-                workspace_bytes=f.workspace_bytes)
+                workspace_bytes=f.workspace_bytes, refine=refine)
 
 
 def cpu_baseline(m):
@@ -132,6 +147,8 @@ def main():
                     help="both: FP64 is the headline value, the mixed form is reported beside it")
     ap.add_argument("--cpu-grid", type=int, default=250, help="m of the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--pcg-tol", type=float, default=1e-10,
+                    help="also time CG on the dense Theta to this residual with each factor (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
     args = ap.parse_args()
@@ -167,7 +184,7 @@ def main():
     entries = {}
     for prec in precs:
         pivot, tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
-        r = run_gpu(w, prec, args.steps, args.warmup, plan, pivot, tau)
+        r = run_gpu(w, prec, args.steps, args.warmup, plan, pivot, tau, args.pcg_tol)
         step_s = r["wall"] / args.steps
         tf = float(np.mean(r["t_factor"]))
         ts = float(np.mean(r["t_solve"]))
@@ -190,6 +207,10 @@ def main():
             "shifted": r["shifted"], "exp_hard": r["exp_hard"], "upload_s": r["t_upload"],
             "workspace_bytes": r["workspace_bytes"],
         }
+        if r["refine"] is not None:
+            entries[prec]["refine"] = r["refine"]
+            log(f"[bench] {prec}: {r['refine']['iterations']} CG iterations to {args.pcg_tol:g} in "
+                f"{r['refine']['seconds_to_tol']:.2f} s")
     head = entries[precs[0]]
     result = {
         "metric": METRIC,
@@ -215,6 +236,8 @@ def main():
                                                                  info["t_schedule_s"]],
         "upload_s": head["upload_s"], "workspace_bytes": head["workspace_bytes"],
     }
+    if "refine" in head:
+        result["refine"] = head["refine"]
     if "mixed" in entries and precs[0] != "mixed":
         result["mixed"] = entries["mixed"]
     if args.cpu_grid > 0:

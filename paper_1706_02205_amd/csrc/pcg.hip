@@ -47,8 +47,9 @@ __device__ __forceinline__ double matern_fast(double r, double inv_ell) {
 }
 
 // Y[i, r0+r] = sum_j Theta(x_i, x_j) X[j, r0+r], j ascending.  x: n x d (any order,
-// X and Y in the same order), d <= 32.
-template <int TWONU, int NR>
+// X and Y in the same order).  D = d for d <= 3 (coordinates in registers), D = 0
+// for any d <= 32 (own coordinates re-read through the cache).
+template <int TWONU, int NR, int D>
 __global__ __launch_bounds__(kRows) void dense_matvec(const double* __restrict__ x, int64_t n, int d, double inv_ell,
                                                       const double* __restrict__ X, int ld, int r0,
                                                       double* __restrict__ Y) {
@@ -56,9 +57,10 @@ __global__ __launch_bounds__(kRows) void dense_matvec(const double* __restrict__
     double* sx = tile;
     double* sv = tile + size_t(kTileJ) * d;
     const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
-    double xi[32];
+    const int64_t ic = i < n ? i : n - 1;
+    double xi[D > 0 ? D : 1];
 #pragma unroll
-    for (int t = 0; t < 32; ++t) xi[t] = (t < d && i < n) ? x[i * d + t] : 0.0;
+    for (int t = 0; t < (D > 0 ? D : 1); ++t) xi[t] = D > 0 ? x[ic * D + t] : 0.0;
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = 0.0;
@@ -67,19 +69,23 @@ __global__ __launch_bounds__(kRows) void dense_matvec(const double* __restrict__
         for (int q = threadIdx.x; q < m * d; q += kRows) sx[q] = x[j0 * d + q];
         for (int q = threadIdx.x; q < m * NR; q += kRows) sv[q] = X[(j0 + q / NR) * ld + r0 + q % NR];
         __syncthreads();
-        if (i < n) {
-            for (int jj = 0; jj < m; ++jj) {
-                double s = 0.0;
+        for (int jj = 0; jj < m; ++jj) {
+            double s = 0.0;
+            if constexpr (D > 0) {
 #pragma unroll
-                for (int t = 0; t < 32; ++t)
-                    if (t < d) {
-                        const double df = xi[t] - sx[jj * d + t];
-                        s = __builtin_fma(df, df, s);
-                    }
-                const double th = matern_fast<TWONU>(__builtin_sqrt(s), inv_ell);
-#pragma unroll
-                for (int r = 0; r < NR; ++r) acc[r] = __builtin_fma(th, sv[jj * NR + r], acc[r]);
+                for (int t = 0; t < D; ++t) {
+                    const double df = xi[t] - sx[jj * D + t];
+                    s = __builtin_fma(df, df, s);
+                }
+            } else {
+                for (int t = 0; t < d; ++t) {
+                    const double df = x[ic * d + t] - sx[jj * d + t];
+                    s = __builtin_fma(df, df, s);
+                }
             }
+            const double th = matern_fast<TWONU>(__builtin_sqrt(s), inv_ell);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] = __builtin_fma(th, sv[jj * NR + r], acc[r]);
         }
         __syncthreads();
     }
@@ -164,27 +170,38 @@ int twonu_of(double nu) {
     return 0;
 }
 
-template <int TWONU>
-hipError_t launch_matvec_t(const double* x, int64_t n, int d, double inv_ell, const double* X, int nrhs, double* Y,
+template <int TWONU, int D>
+hipError_t launch_matvec_d(const double* x, int64_t n, int d, double inv_ell, const double* X, int nrhs, double* Y,
                            hipStream_t s) {
     for (int r0 = 0; r0 < nrhs; r0 += kMaxNr) {
         const int nr = std::min(kMaxNr, nrhs - r0);
         const size_t lds = size_t(kTileJ) * (d + nr) * sizeof(double);
         const dim3 g(blocks_for(n, kRows));
         switch (nr) {
-            case 1: dense_matvec<TWONU, 1><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 2: dense_matvec<TWONU, 2><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 3: dense_matvec<TWONU, 3><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 4: dense_matvec<TWONU, 4><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 5: dense_matvec<TWONU, 5><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 6: dense_matvec<TWONU, 6><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 7: dense_matvec<TWONU, 7><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            default: dense_matvec<TWONU, 8><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            case 1: dense_matvec<TWONU, 1, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            case 2: dense_matvec<TWONU, 2, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            case 3: dense_matvec<TWONU, 3, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            case 4: dense_matvec<TWONU, 4, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            case 5: dense_matvec<TWONU, 5, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            case 6: dense_matvec<TWONU, 6, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            case 7: dense_matvec<TWONU, 7, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
+            default: dense_matvec<TWONU, 8, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int TWONU>
+hipError_t launch_matvec_t(const double* x, int64_t n, int d, double inv_ell, const double* X, int nrhs, double* Y,
+                           hipStream_t s) {
+    switch (d) {
+        case 1: return launch_matvec_d<TWONU, 1>(x, n, d, inv_ell, X, nrhs, Y, s);
+        case 2: return launch_matvec_d<TWONU, 2>(x, n, d, inv_ell, X, nrhs, Y, s);
+        case 3: return launch_matvec_d<TWONU, 3>(x, n, d, inv_ell, X, nrhs, Y, s);
+        default: return launch_matvec_d<TWONU, 0>(x, n, d, inv_ell, X, nrhs, Y, s);
+    }
 }
 
 hipError_t launch_matvec(int tn, const double* x, int64_t n, int d, double ell, const double* X, int nrhs, double* Y,

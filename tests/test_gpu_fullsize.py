@@ -87,3 +87,24 @@ def test_solve_backward_error(big):
     resid = np.abs(bh - Lm @ (Lm.T @ xh))
     scale = Labs @ (Labs.T @ np.abs(xh))
     assert np.max(resid / scale) < 1e-10
+
+
+def test_pcg_true_residual_on_sampled_rows(big):
+    """CG with the factor as preconditioner at full size: the true residual b - Theta x,
+    recomputed by the oracle on 200 random rows, matches the 1e-10 target in RMS."""
+    import torch
+    import paper_1706_02205_amd as K
+    w = big["w"]
+    print("[gpu] full size: pcg", flush=True)
+    plan = K.analyze(w.points, w.rho)
+    f = K.Factor(plan, "mixed")
+    xd = torch.from_numpy(w.points).to("cuda")
+    f.factorize(xd, w.nu, w.lengthscale, "shift", 1e-6)
+    sol, info = f.pcg(xd, torch.from_numpy(big["b"]).to("cuda"), w.nu, w.lengthscale, tol=1e-10)
+    sol = sol.cpu().numpy()
+    assert info.converged and info.max_rel_residual <= 1e-10
+    rows = np.random.default_rng(2).integers(0, w.n, 200)
+    r = big["b"][rows] - O.dense_matvec_rows(w.points, sol, w.nu, w.lengthscale, rows)
+    rms_rel = np.sqrt((r ** 2).mean(axis=0) * w.n) / np.linalg.norm(big["b"], axis=0)
+    print(f"[gpu] full size: {info.iterations} CG iterations, sampled true residual {rms_rel.max():.2e}", flush=True)
+    assert np.all(rms_rel < 3e-10)
