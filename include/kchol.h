@@ -68,6 +68,7 @@ typedef struct {
 
 typedef struct kc_plan kc_plan;
 typedef struct kc_factor kc_factor;
+typedef struct kc_graph kc_graph;
 
 typedef struct {
     int64_t n;
@@ -83,6 +84,7 @@ typedef struct {
     double t_order_s;     /* host time of the maximin ordering */
     double t_pattern_s;   /* host time of the pattern (CSC + CSR) */
     double t_schedule_s;  /* host time of levels and work units */
+    int32_t ninst;        /* independent problems in the plan (1 unless built by kc_analyze_batched) */
 } kc_plan_info_t;
 
 typedef struct {
@@ -106,6 +108,13 @@ const char *kc_last_error(void);
  * lowest original index.  *out is library-owned until kc_plan_destroy. */
 kc_status kc_analyze(const double *x, int64_t n, int32_t d, double rho, kc_rule rule, int32_t nthreads,
                      kc_plan **out);
+/* A batch of independent problems as one plan: instance i is the next counts[i]
+ * rows of x (N_total x d).  Each instance is analysed on its own (the same
+ * ordering and pattern as kc_analyze on its points, positions shifted by the
+ * points before it); their DAG levels are merged so that one launch per level
+ * factors every instance at that depth.  Instances run on separate host threads. */
+kc_status kc_analyze_batched(const double *x, const int64_t *counts, int32_t ninst, int32_t d, double rho,
+                             kc_rule rule, int32_t nthreads, kc_plan **out);
 kc_status kc_plan_info(const kc_plan *plan, kc_plan_info_t *info);
 /* Copies the ordering and pattern into caller buffers (any may be NULL):
  * perm[N] (maximin position -> original index), l[N], colptr[N+1],
@@ -135,6 +144,11 @@ kc_status kc_factor_create(const kc_plan *plan, kc_prec prec, void *ws_dev, size
 kc_status kc_factorize(kc_factor *f, const double *x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
                        int32_t count_updates, void *stream);
 
+/* kc_factorize for a batch plan: every instance shares nu, instance i uses the
+ * lengthscale ell_dev[i] (device array of ninst doubles, each finite and > 0). */
+kc_status kc_factorize_batched(kc_factor *f, const double *x_dev, double nu, const double *ell_dev, kc_pivot pivot,
+                               double tau, int32_t count_updates, void *stream);
+
 /* Theta on S alone, in CSC order (nnz float64) -- the entries the
  * factorization starts from.  Requires kc_factor_create. */
 kc_status kc_theta(kc_factor *f, const double *x_dev, kc_kernel kernel, double *theta_dev, void *stream);
@@ -156,6 +170,25 @@ kc_status kc_factor_stats(kc_factor *f, kc_factor_stats_t *stats);
 kc_status kc_factor_export_L(const kc_factor *f, double *vals);
 
 void kc_factor_destroy(kc_factor *f);
+
+/* Autotuner: times the factorization (reps repetitions after a warm-up) with 1,
+ * 2 and 4 wavefronts per workgroup -- each fitting the staged rows in LDS --
+ * and keeps the fastest for this factor.  Results are bitwise identical for
+ * every choice.  For a batch plan pass ell_dev (and ell is ignored), else NULL. */
+kc_status kc_factor_tune(kc_factor *f, const double *x_dev, double nu, double ell, const double *ell_dev,
+                         kc_pivot pivot, double tau, int32_t reps, void *stream, int32_t *chosen_wpb);
+
+/* Captures factorize + solve of this factor into a HIP graph (on an internal
+ * stream; no memory is allocated by the captured work) so that one
+ * kc_graph_launch replays every level launch.  Arguments are those of
+ * kc_factorize/kc_factorize_batched and kc_solve; the pointers are baked into the
+ * graph and must stay valid.  Replays on a stream are ordered like any other
+ * work on it. */
+kc_status kc_graph_create(kc_factor *f, const double *x_dev, double nu, double ell, const double *ell_dev,
+                          kc_pivot pivot, double tau, const double *b_dev, double *sol_dev, int32_t nrhs,
+                          void *scratch_dev, size_t scratch_bytes, kc_graph **out);
+kc_status kc_graph_launch(kc_graph *g, void *stream);
+void kc_graph_destroy(kc_graph *g);
 
 /* ---------------------------------------------------------------- refinement */
 

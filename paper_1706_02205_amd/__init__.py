@@ -20,7 +20,7 @@ import numpy as np
 from . import _lib
 from ._lib import KCholError
 
-__all__ = ["analyze", "dense_matvec", "Plan", "Factor", "KCholError"]
+__all__ = ["analyze", "analyze_batched", "dense_matvec", "Plan", "Factor", "Graph", "KCholError"]
 
 _RULES = {"max": _lib.KC_RULE_MAX, "min": _lib.KC_RULE_MIN}
 _PRECS = {"fp64": _lib.KC_FP64, "mixed": _lib.KC_MIXED}
@@ -34,9 +34,10 @@ def _ptr(a: np.ndarray):
 class Plan:
     """Host analysis: maximin ordering, pattern S and the elimination schedule."""
 
-    def __init__(self, handle, n: int, d: int):
+    def __init__(self, handle, n: int, d: int, counts=None):
         self._h = handle
         self.n, self.d = n, d
+        self.counts = counts  # points per instance for a batch plan, else None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -84,6 +85,20 @@ def analyze(x: np.ndarray, rho: float, rule: str = "max", nthreads: int = 0) -> 
     _lib.check(_lib.load().kc_analyze(_ptr(x), n, d, float(rho), _RULES[rule], int(nthreads), C.byref(h)),
                "kc_analyze")
     return Plan(h, n, d)
+
+
+def analyze_batched(xs, rho: float, rule: str = "max", nthreads: int = 0) -> Plan:
+    """Independent problems (a list of (n_i, d) arrays) analysed as one block-diagonal plan."""
+    xs = [np.ascontiguousarray(x, dtype=np.float64) for x in xs]
+    d = xs[0].shape[1]
+    if any(x.ndim != 2 or x.shape[1] != d for x in xs):
+        raise ValueError("every instance must be (n_i, d) with the same d")
+    counts = np.array([x.shape[0] for x in xs], dtype=np.int64)
+    allx = np.ascontiguousarray(np.concatenate(xs))
+    h = C.c_void_p()
+    _lib.check(_lib.load().kc_analyze_batched(_ptr(allx), _ptr(counts), len(xs), d, float(rho), _RULES[rule],
+                                              int(nthreads), C.byref(h)), "kc_analyze_batched")
+    return Plan(h, int(counts.sum()), d, counts)
 
 
 def _stream_ptr(stream=None):
@@ -159,6 +174,31 @@ class Factor:
                                             _PIVOTS[pivot], float(tau), int(bool(count_updates)),
                                             _stream_ptr(stream)), "kc_factorize")
 
+    def factorize_batched(self, x_dev, nu: float, ell_dev, pivot: str = "zero", tau: float = 0.0,
+                          count_updates: bool = False, stream=None) -> None:
+        """Factor every instance of a batch plan; ell_dev holds one lengthscale per instance (device)."""
+        self._check_points(x_dev)
+        _lib.check(_lib.load().kc_factorize_batched(self._h, C.c_void_p(x_dev.data_ptr()), float(nu),
+                                                    C.c_void_p(ell_dev.data_ptr()), _PIVOTS[pivot], float(tau),
+                                                    int(bool(count_updates)), _stream_ptr(stream)),
+                   "kc_factorize_batched")
+
+    def tune(self, x_dev, nu: float, lengthscale: float = 0.0, ell_dev=None, pivot: str = "zero", tau: float = 0.0,
+             reps: int = 3, stream=None) -> int:
+        """Pick the fastest wavefronts-per-workgroup for this factor by timing it; returns the choice."""
+        self._check_points(x_dev)
+        w = C.c_int32()
+        _lib.check(_lib.load().kc_factor_tune(self._h, C.c_void_p(x_dev.data_ptr()), float(nu), float(lengthscale),
+                                              C.c_void_p(ell_dev.data_ptr()) if ell_dev is not None else None,
+                                              _PIVOTS[pivot], float(tau), int(reps), _stream_ptr(stream),
+                                              C.byref(w)), "kc_factor_tune")
+        return int(w.value)
+
+    def capture(self, x_dev, b_dev, nu: float, lengthscale: float = 0.0, ell_dev=None, pivot: str = "zero",
+                tau: float = 0.0) -> "Graph":
+        """Capture factorize + solve into a HIP graph; returns the graph and its output tensor."""
+        return Graph(self, x_dev, b_dev, nu, lengthscale, ell_dev, pivot, tau)
+
     def theta(self, x_dev, nu: float, lengthscale: float, stream=None):
         """Theta on S in CSC order (the factorization's starting entries)."""
         import torch
@@ -223,3 +263,35 @@ class Factor:
             raise ValueError("points must be a contiguous float64 CUDA tensor")
         if tuple(x_dev.shape) != (self.n, self.d):
             raise ValueError(f"points must have shape ({self.n}, {self.d})")
+
+
+class Graph:
+    """factorize + solve of one factor captured as a HIP graph (see Factor.capture)."""
+
+    def __init__(self, factor: "Factor", x_dev, b_dev, nu, lengthscale, ell_dev, pivot, tau):
+        import torch
+        factor._check_points(x_dev)
+        nrhs = 1 if b_dev.dim() == 1 else int(b_dev.shape[1])
+        nb = C.c_size_t()
+        _lib.check(_lib.load().kc_solve_bytes(factor._h, nrhs, C.byref(nb)), "kc_solve_bytes")
+        self.scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=b_dev.device)
+        self.out = torch.empty_like(b_dev)
+        self._keep = (factor, x_dev, b_dev, ell_dev)
+        h = C.c_void_p()
+        _lib.check(_lib.load().kc_graph_create(factor._h, C.c_void_p(x_dev.data_ptr()), float(nu), float(lengthscale),
+                                               C.c_void_p(ell_dev.data_ptr()) if ell_dev is not None else None,
+                                               _PIVOTS[pivot], float(tau), C.c_void_p(b_dev.data_ptr()),
+                                               C.c_void_p(self.out.data_ptr()), nrhs,
+                                               C.c_void_p(self.scratch.data_ptr()), self.scratch.numel(),
+                                               C.byref(h)), "kc_graph_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().kc_graph_launch(self._h, _stream_ptr(stream)), "kc_graph_launch")
+        return self.out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None and _lib._LIB is not None:
+            _lib._LIB.kc_graph_destroy(h)
+            self._h = None

@@ -21,7 +21,8 @@ class kc_plan_info_t(C.Structure):
     _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("rule", C.c_int32), ("rho", C.c_double),
                 ("nnz", C.c_int64), ("max_col", C.c_int64), ("max_row", C.c_int64),
                 ("nlevels", C.c_int32), ("nrlevels", C.c_int32), ("nunits", C.c_int64),
-                ("t_order_s", C.c_double), ("t_pattern_s", C.c_double), ("t_schedule_s", C.c_double)]
+                ("t_order_s", C.c_double), ("t_pattern_s", C.c_double), ("t_schedule_s", C.c_double),
+                ("ninst", C.c_int32)]
 
 
 class kc_pcg_info_t(C.Structure):
@@ -37,7 +38,8 @@ class kc_factor_stats_t(C.Structure):
 EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "kc_plan_export", "kc_plan_levels",
             "kc_plan_destroy", "kc_factor_bytes", "kc_factor_create", "kc_factorize", "kc_theta", "kc_solve_bytes",
             "kc_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
-            "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg")
+            "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
+            "kc_factor_tune", "kc_graph_create", "kc_graph_launch", "kc_graph_destroy")
 
 _LIB = None
 
@@ -81,6 +83,12 @@ def load():
         "kc_dense_matvec": (C.c_int, [vp, i64, i32, kc_kernel, vp, vp, i32, vp]),
         "kc_pcg_bytes": (C.c_int, [vp, i32, P(sz)]),
         "kc_pcg": (C.c_int, [vp, vp, kc_kernel, vp, vp, i32, f64, i32, vp, sz, vp, P(kc_pcg_info_t)]),
+        "kc_analyze_batched": (C.c_int, [vp, vp, i32, i32, f64, C.c_int, i32, P(vp)]),
+        "kc_factorize_batched": (C.c_int, [vp, vp, f64, vp, C.c_int, f64, i32, vp]),
+        "kc_factor_tune": (C.c_int, [vp, vp, f64, f64, vp, C.c_int, f64, i32, vp, P(i32)]),
+        "kc_graph_create": (C.c_int, [vp, vp, f64, f64, vp, C.c_int, f64, vp, vp, i32, vp, sz, P(vp)]),
+        "kc_graph_launch": (C.c_int, [vp, vp]),
+        "kc_graph_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

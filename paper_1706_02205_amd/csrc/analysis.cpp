@@ -425,3 +425,118 @@ void build_schedule(Plan& p, int nthreads) {
 }
 
 }  // namespace kc
+
+namespace kc {
+
+// The union of independent problems is one problem whose pattern is block
+// diagonal: positions, rows and columns of instance i are shifted by the
+// number of points before it, and its DAG levels are merged level by level
+// with the other instances' (columns of different instances never depend on
+// each other), so one launch per level serves every instance at that depth.
+void merge_plans(const std::vector<Plan>& parts, Plan& out) {
+    const int32_t ni = int32_t(parts.size());
+    out = Plan();
+    out.ninst = ni;
+    out.d = parts.empty() ? 0 : parts[0].d;
+    out.rho = parts.empty() ? 0.0 : parts[0].rho;
+    out.rule = parts.empty() ? 0 : parts[0].rule;
+    out.inst_off.assign(size_t(ni + 1), 0);
+    int64_t nnz = 0, nnzr = 0;
+    for (int32_t i = 0; i < ni; ++i) {
+        out.inst_off[i + 1] = out.inst_off[i] + parts[i].n;
+        nnz += parts[i].nnz();
+        nnzr += parts[i].nnz_rows();
+        out.nlevels = std::max(out.nlevels, parts[i].nlevels);
+        out.nrlevels = std::max(out.nrlevels, parts[i].nrlevels);
+        out.max_col = std::max(out.max_col, parts[i].max_col);
+        out.max_row = std::max(out.max_row, parts[i].max_row);
+    }
+    const int64_t n = out.inst_off[ni];
+    out.n = n;
+    out.perm.resize(size_t(n));
+    out.l.resize(size_t(n));
+    out.xh.resize(size_t(n) * out.d);
+    out.spatial.resize(size_t(n));
+    out.inst.resize(size_t(n));
+    out.level.resize(size_t(n));
+    out.colptr.assign(size_t(n + 1), 0);
+    out.rowidx.resize(size_t(nnz));
+    out.rowptr.assign(size_t(n + 1), 0);
+    out.rowend.resize(size_t(n));
+    out.colidx.resize(size_t(nnzr));
+    out.csc2csr.resize(size_t(nnz));
+    int64_t e0 = 0, q0 = 0;
+    for (int32_t i = 0; i < ni; ++i) {
+        const Plan& p = parts[i];
+        const int64_t b = out.inst_off[i];
+        for (int64_t k = 0; k < p.n; ++k) {
+            out.perm[b + k] = int32_t(b + p.perm[k]);
+            out.l[b + k] = p.l[k];
+            out.spatial[b + k] = int32_t(b + p.spatial[k]);
+            out.inst[b + k] = i;
+            out.level[b + k] = p.level[k];
+            out.colptr[b + k + 1] = e0 + p.colptr[k + 1];
+            out.rowptr[b + k + 1] = q0 + p.rowptr[k + 1];
+            out.rowend[b + k] = q0 + p.rowend[k];
+        }
+        std::copy(p.xh.begin(), p.xh.end(), out.xh.begin() + b * out.d);
+        for (int64_t e = 0; e < p.nnz(); ++e) {
+            out.rowidx[e0 + e] = int32_t(b + p.rowidx[e]);
+            out.csc2csr[e0 + e] = uint32_t(q0 + p.csc2csr[e]);
+        }
+        for (int64_t q = 0; q < p.nnz_rows(); ++q)
+            out.colidx[q0 + q] = p.colidx[q] == INT32_MAX ? INT32_MAX : int32_t(b + p.colidx[q]);
+        e0 += p.nnz();
+        q0 += p.nnz_rows();
+    }
+    // level-major merge of units and forward rows
+    out.unit_off.assign(size_t(out.nlevels + 1), 0);
+    out.fwd_off.assign(size_t(out.nlevels + 1), 0);
+    for (int32_t v = 0; v < out.nlevels; ++v) {
+        int64_t u = 0, r = 0;
+        for (const Plan& p : parts)
+            if (v < p.nlevels) {
+                u += p.unit_off[v + 1] - p.unit_off[v];
+                r += p.fwd_off[v + 1] - p.fwd_off[v];
+            }
+        out.unit_off[v + 1] = out.unit_off[v] + u;
+        out.fwd_off[v + 1] = out.fwd_off[v] + r;
+    }
+    out.units.resize(size_t(out.unit_off[out.nlevels]));
+    out.fwd_rows.resize(size_t(n));
+    for (int32_t v = 0; v < out.nlevels; ++v) {
+        int64_t u = out.unit_off[v], r = out.fwd_off[v];
+        for (int32_t i = 0; i < ni; ++i) {
+            const Plan& p = parts[i];
+            if (v >= p.nlevels) continue;
+            const int32_t b = int32_t(out.inst_off[i]);
+            for (int64_t t = p.unit_off[v]; t < p.unit_off[v + 1]; ++t)
+                out.units[size_t(u++)] = Unit{b + p.units[t].col, p.units[t].first};
+            for (int64_t t = p.fwd_off[v]; t < p.fwd_off[v + 1]; ++t) out.fwd_rows[size_t(r++)] = b + p.fwd_rows[t];
+        }
+    }
+    out.bwd_off.assign(size_t(out.nrlevels + 1), 0);
+    for (int32_t v = 0; v < out.nrlevels; ++v) {
+        int64_t c = 0;
+        for (const Plan& p : parts)
+            if (v < p.nrlevels) c += p.bwd_off[v + 1] - p.bwd_off[v];
+        out.bwd_off[v + 1] = out.bwd_off[v] + c;
+    }
+    out.bwd_cols.resize(size_t(n));
+    for (int32_t v = 0; v < out.nrlevels; ++v) {
+        int64_t c = out.bwd_off[v];
+        for (int32_t i = 0; i < ni; ++i) {
+            const Plan& p = parts[i];
+            if (v >= p.nrlevels) continue;
+            const int32_t b = int32_t(out.inst_off[i]);
+            for (int64_t t = p.bwd_off[v]; t < p.bwd_off[v + 1]; ++t) out.bwd_cols[size_t(c++)] = b + p.bwd_cols[t];
+        }
+    }
+    for (const Plan& p : parts) {
+        out.t_order += p.t_order;
+        out.t_pattern += p.t_pattern;
+        out.t_schedule += p.t_schedule;
+    }
+}
+
+}  // namespace kc

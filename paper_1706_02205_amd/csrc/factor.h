@@ -33,6 +33,8 @@ struct kc_factor {
     int32_t* bwd_short = nullptr;
     kc::LongCol* bwd_long = nullptr;
     kc::BwdChunk* bwd_chunks = nullptr;
+    int32_t* inst = nullptr;   // instance of each position (batches only)
+    int32_t ninst = 1;
     // host schedule
     std::vector<int64_t> unit_off, fwd_off, short_off, long_off, chunk_off;
     int64_t max_slots = 0;    // partial sums needed by the widest reverse level

@@ -21,6 +21,8 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <atomic>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -167,13 +169,14 @@ __device__ __forceinline__ int xcd_block() {
 // VT = double: FP64.  VT = float (MIXED): off-diagonal Theta, updates and the
 // stored L in FP32; the pivot accumulates exact FP32 x FP32 products in FP64,
 // and sqrt and the division by L_jj are FP64.
-template <int TWONU, bool COUNT, typename VT, int WPB>
+template <int TWONU, bool COUNT, typename VT, int WPB, bool BATCH>
 __global__ __launch_bounds__(WPB * kWave) void ichol_level(
     const Unit* __restrict__ units, int64_t ubeg, int64_t uend, const int64_t* __restrict__ colptr,
     const int32_t* __restrict__ rowidx, const uint32_t* __restrict__ csc2csr, const int64_t* __restrict__ rowptr,
     const int64_t* __restrict__ rowend, const int32_t* __restrict__ colidx, VT* __restrict__ Lv,
-    VT* __restrict__ Lcsc, double* __restrict__ diag, const double* __restrict__ xh, int d, double ell, int policy,
-    double tau, int cap, unsigned long long* __restrict__ counters) {
+    VT* __restrict__ Lcsc, double* __restrict__ diag, const double* __restrict__ xh, int d, double ell,
+    const int32_t* __restrict__ inst, const double* __restrict__ ells, int policy, double tau, int cap,
+    unsigned long long* __restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
@@ -207,6 +210,7 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(
     const int64_t e = colptr[j] + first + lane;
     const bool active = e < colptr[j + 1];
     const int k = active ? rowidx[e] : j;
+    if constexpr (BATCH) ell = ells[inst[j]];  // lengthscale of j's instance
     int hard = 0;
     VT acc;
     if constexpr (sizeof(VT) == 8)
@@ -516,7 +520,7 @@ BwdSchedule backward_schedule(const kc::Plan& p) {
 
 struct Layout {
     size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, L, Lcsc, diag, units, fwd, bshort,
-        blong, bchunks, total;
+        blong, bchunks, inst, total;
 };
 
 Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
@@ -546,6 +550,7 @@ Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
     o.bshort = take(b.shortc.size() * sizeof(int32_t));
     o.blong = take(b.longc.size() * sizeof(kc::LongCol));
     o.bchunks = take(b.chunks.size() * sizeof(kc::BwdChunk));
+    o.inst = take(p.ninst > 1 ? n * sizeof(int32_t) : 0);
     o.total = at;
     return o;
 }
@@ -565,19 +570,27 @@ int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 1 + 15) / 16 * 
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 template <typename VT>
-kc_status launch_level(const kc_factor* f, int tn, bool cnt, int64_t ub, int64_t ue, double ell, int pol, double tau,
-                       hipStream_t s) {
+kc_status launch_level(const kc_factor* f, int tn, bool cnt, int64_t ub, int64_t ue, double ell, const double* ells,
+                       int pol, double tau, hipStream_t s) {
     VT* Lv = static_cast<VT*>(f->L);
     VT* Lc = static_cast<VT*>(f->Lcsc);
     const size_t lds = size_t(f->wpb) * f->cap * (sizeof(VT) + sizeof(int32_t));
     const dim3 grid(grid_for(ue - ub, f->wpb));
+    const bool batch = ells != nullptr;
 #define KC_ARGS                                                                                           \
     f->units, ub, ue, f->colptr, f->rowidx, f->csc2csr, f->rowptr, f->rowend, f->colidx, Lv, Lc, f->diag, \
-        f->xh, f->d, ell, pol, tau, f->cap, f->counters
+        f->xh, f->d, ell, f->inst, ells, pol, tau, f->cap, f->counters
 #define KC_CASE(TN, C)                                                                                    \
     if (tn == TN && cnt == C) {                                                                           \
-        if (f->wpb == 4) ichol_level<TN, C, VT, 4><<<grid, 4 * kWave, lds, s>>>(KC_ARGS);                   \
-        else ichol_level<TN, C, VT, 1><<<grid, kWave, lds, s>>>(KC_ARGS);                                  \
+        if (batch) {                                                                                      \
+            if (f->wpb == 4) ichol_level<TN, C, VT, 4, true><<<grid, 4 * kWave, lds, s>>>(KC_ARGS);         \
+            else if (f->wpb == 2) ichol_level<TN, C, VT, 2, true><<<grid, 2 * kWave, lds, s>>>(KC_ARGS);    \
+            else ichol_level<TN, C, VT, 1, true><<<grid, kWave, lds, s>>>(KC_ARGS);                        \
+        } else {                                                                                          \
+            if (f->wpb == 4) ichol_level<TN, C, VT, 4, false><<<grid, 4 * kWave, lds, s>>>(KC_ARGS);        \
+            else if (f->wpb == 2) ichol_level<TN, C, VT, 2, false><<<grid, 2 * kWave, lds, s>>>(KC_ARGS);   \
+            else ichol_level<TN, C, VT, 1, false><<<grid, kWave, lds, s>>>(KC_ARGS);                       \
+        }                                                                                                 \
     }
     KC_CASE(1, false)
     KC_CASE(1, true)
@@ -677,13 +690,7 @@ int32_t kc_device_count(void) {
     return c;
 }
 
-kc_status kc_analyze(const double* x, int64_t n, int32_t d, double rho, kc_rule rule, int32_t nthreads,
-                     kc_plan** out) {
-    if (!out) {
-        kc::set_error("kc_analyze: out is NULL");
-        return KC_EINVAL;
-    }
-    *out = nullptr;
+static kc_status check_points(const double* x, int64_t n, int32_t d, double rho, kc_rule rule) {
     if (!x || n < 1 || d < 1 || !(rho > 0.0) || !std::isfinite(rho) || (rule != KC_RULE_MAX && rule != KC_RULE_MIN)) {
         kc::set_error("kc_analyze: need x != NULL, n >= 1, d >= 1, finite rho > 0, rule MAX or MIN");
         return KC_EINVAL;
@@ -697,38 +704,105 @@ kc_status kc_analyze(const double* x, int64_t n, int32_t d, double rho, kc_rule 
             kc::set_error("kc_analyze: non-finite coordinate");
             return KC_EINVAL;
         }
+    return KC_OK;
+}
+
+static void analyze_one(const double* x, int64_t n, int32_t d, double rho, kc_rule rule, int32_t nthreads,
+                        kc::Plan& p) {
+    p.n = n;
+    p.d = d;
+    p.rho = rho;
+    p.rule = rule;
+    p.perm.resize(size_t(n));
+    p.l.resize(size_t(n));
+    auto t0 = std::chrono::steady_clock::now();
+    kc::maximin_order(x, n, d, nthreads, p.perm.data(), p.l.data());
+    auto t1 = std::chrono::steady_clock::now();
+    p.xh.resize(size_t(n) * d);
+    for (int64_t k = 0; k < n; ++k)
+        for (int t = 0; t < d; ++t) p.xh[size_t(k) * d + t] = x[size_t(p.perm[k]) * d + t];
+    kc::build_pattern(p, nthreads);
+    auto t2 = std::chrono::steady_clock::now();
+    if (p.nnz() < (int64_t(1) << 32) && p.nnz_rows() < (int64_t(1) << 32)) kc::build_schedule(p, nthreads);
+    auto t3 = std::chrono::steady_clock::now();
+    p.t_order = std::chrono::duration<double>(t1 - t0).count();
+    p.t_pattern = std::chrono::duration<double>(t2 - t1).count();
+    p.t_schedule = std::chrono::duration<double>(t3 - t2).count();
+}
+
+kc_status kc_analyze(const double* x, int64_t n, int32_t d, double rho, kc_rule rule, int32_t nthreads,
+                     kc_plan** out) {
+    if (!out) {
+        kc::set_error("kc_analyze: out is NULL");
+        return KC_EINVAL;
+    }
+    *out = nullptr;
+    const kc_status st = check_points(x, n, d, rho, rule);
+    if (st != KC_OK) return st;
     kc_plan* plan = new (std::nothrow) kc_plan;
     if (!plan) return KC_ENOMEM;
     try {
-        kc::Plan& p = plan->p;
-        p.n = n;
-        p.d = d;
-        p.rho = rho;
-        p.rule = rule;
-        p.perm.resize(size_t(n));
-        p.l.resize(size_t(n));
-        auto t0 = std::chrono::steady_clock::now();
-        kc::maximin_order(x, n, d, nthreads, p.perm.data(), p.l.data());
-        auto t1 = std::chrono::steady_clock::now();
-        p.xh.resize(size_t(n) * d);
-        for (int64_t k = 0; k < n; ++k)
-            for (int t = 0; t < d; ++t) p.xh[size_t(k) * d + t] = x[size_t(p.perm[k]) * d + t];
-        kc::build_pattern(p, nthreads);
-        if (p.nnz() >= (int64_t(1) << 32) || p.nnz_rows() >= (int64_t(1) << 32)) {
-            delete plan;
-            kc::set_error("kc_analyze: nnz(S) >= 2^32");
-            return KC_ERANGE;
-        }
-        auto t2 = std::chrono::steady_clock::now();
-        kc::build_schedule(p, nthreads);
-        auto t3 = std::chrono::steady_clock::now();
-        p.t_order = std::chrono::duration<double>(t1 - t0).count();
-        p.t_pattern = std::chrono::duration<double>(t2 - t1).count();
-        p.t_schedule = std::chrono::duration<double>(t3 - t2).count();
+        analyze_one(x, n, d, rho, rule, nthreads, plan->p);
     } catch (const std::bad_alloc&) {
         delete plan;
         kc::set_error("kc_analyze: out of host memory");
         return KC_ENOMEM;
+    }
+    if (plan->p.nnz() >= (int64_t(1) << 32) || plan->p.nnz_rows() >= (int64_t(1) << 32)) {
+        delete plan;
+        kc::set_error("kc_analyze: nnz(S) >= 2^32");
+        return KC_ERANGE;
+    }
+    *out = plan;
+    return KC_OK;
+}
+
+kc_status kc_analyze_batched(const double* x, const int64_t* counts, int32_t ninst, int32_t d, double rho,
+                             kc_rule rule, int32_t nthreads, kc_plan** out) {
+    if (!out) return KC_EINVAL;
+    *out = nullptr;
+    if (!counts || ninst < 1) {
+        kc::set_error("kc_analyze_batched: need counts and ninst >= 1");
+        return KC_EINVAL;
+    }
+    std::vector<int64_t> off(size_t(ninst) + 1, 0);
+    for (int32_t i = 0; i < ninst; ++i) {
+        if (counts[i] < 1) {
+            kc::set_error("kc_analyze_batched: every instance needs at least one point");
+            return KC_EINVAL;
+        }
+        off[i + 1] = off[i] + counts[i];
+    }
+    const kc_status st = check_points(x, off[ninst], d, rho, rule);
+    if (st != KC_OK) return st;
+    kc_plan* plan = new (std::nothrow) kc_plan;
+    if (!plan) return KC_ENOMEM;
+    try {
+        std::vector<kc::Plan> parts(static_cast<size_t>(ninst));
+        int nt = nthreads > 0 ? nthreads : int(std::max(1u, std::thread::hardware_concurrency()));
+        nt = std::min(nt, ninst);
+        std::atomic<int32_t> next{0};
+        auto work = [&]() {
+            for (;;) {
+                const int32_t i = next.fetch_add(1);
+                if (i >= ninst) break;
+                analyze_one(x + size_t(off[i]) * d, counts[i], d, rho, rule, 1, parts[size_t(i)]);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+        work();
+        for (auto& th : pool) th.join();
+        kc::merge_plans(parts, plan->p);
+    } catch (const std::bad_alloc&) {
+        delete plan;
+        kc::set_error("kc_analyze_batched: out of host memory");
+        return KC_ENOMEM;
+    }
+    if (plan->p.nnz() >= (int64_t(1) << 32) || plan->p.nnz_rows() >= (int64_t(1) << 32)) {
+        delete plan;
+        kc::set_error("kc_analyze_batched: nnz(S) of the batch >= 2^32");
+        return KC_ERANGE;
     }
     *out = plan;
     return KC_OK;
@@ -750,6 +824,7 @@ kc_status kc_plan_info(const kc_plan* plan, kc_plan_info_t* info) {
     info->t_order_s = p.t_order;
     info->t_pattern_s = p.t_pattern;
     info->t_schedule_s = p.t_schedule;
+    info->ninst = p.ninst;
     return KC_OK;
 }
 
@@ -837,6 +912,8 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->bwd_short = reinterpret_cast<int32_t*>(base + o.bshort);
     f->bwd_long = reinterpret_cast<kc::LongCol*>(base + o.blong);
     f->bwd_chunks = reinterpret_cast<kc::BwdChunk*>(base + o.bchunks);
+    f->inst = p.ninst > 1 ? reinterpret_cast<int32_t*>(base + o.inst) : nullptr;
+    f->ninst = p.ninst;
     f->unit_off = p.unit_off;
     f->fwd_off = p.fwd_off;
     f->short_off = bs.short_off;
@@ -864,6 +941,7 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     if (!bs.chunks.empty())
         KC_HIP(hipMemcpyAsync(f->bwd_chunks, bs.chunks.data(), bs.chunks.size() * sizeof(kc::BwdChunk),
                               hipMemcpyHostToDevice, s));
+    if (f->inst) KC_HIP(hipMemcpyAsync(f->inst, p.inst.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     // the sources are pageable host memory owned by the plan and bs: wait for the copies
     KC_HIP(hipStreamSynchronize(s));
     f->last = s;
@@ -871,12 +949,11 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     return KC_OK;
 }
 
-kc_status kc_factorize(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
-                       int32_t count_updates, void* stream) {
-    if (!f || !x_dev) return KC_EINVAL;
-    const int tn = twonu_of(kernel.nu);
-    if (!tn || !(kernel.lengthscale > 0.0) || !std::isfinite(kernel.lengthscale)) {
-        kc::set_error("kc_factorize: nu must be 0.5, 1.5 or 2.5 and the lengthscale finite and positive");
+static kc_status factorize_impl(kc_factor* f, const double* x_dev, double nu, double ell, const double* ells,
+                                kc_pivot pivot, double tau, int32_t count_updates, void* stream) {
+    const int tn = twonu_of(nu);
+    if (!tn) {
+        kc::set_error("kc_factorize: nu must be 0.5, 1.5 or 2.5");
         return KC_EINVAL;
     }
     if (pivot != KC_PIVOT_ZERO && pivot != KC_PIVOT_SHIFT) return KC_EINVAL;
@@ -895,14 +972,38 @@ kc_status kc_factorize(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_p
         const int64_t ub = f->unit_off[v], ue = f->unit_off[v + 1];
         if (ue <= ub) continue;
         const kc_status st = f->prec == KC_FP64
-                                 ? launch_level<double>(f, tn, cnt, ub, ue, kernel.lengthscale, int(pivot), tau, s)
-                                 : launch_level<float>(f, tn, cnt, ub, ue, kernel.lengthscale, int(pivot), tau, s);
+                                 ? launch_level<double>(f, tn, cnt, ub, ue, ell, ells, int(pivot), tau, s)
+                                 : launch_level<float>(f, tn, cnt, ub, ue, ell, ells, int(pivot), tau, s);
         if (st != KC_OK) return st;
     }
     f->factorized = true;
     f->counted = cnt;
     f->last = s;
     return KC_OK;
+}
+
+kc_status kc_factorize(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
+                       int32_t count_updates, void* stream) {
+    if (!f || !x_dev) return KC_EINVAL;
+    if (f->ninst > 1) {
+        kc::set_error("kc_factorize: the plan holds a batch; use kc_factorize_batched");
+        return KC_EINVAL;
+    }
+    if (!(kernel.lengthscale > 0.0) || !std::isfinite(kernel.lengthscale)) {
+        kc::set_error("kc_factorize: the lengthscale must be finite and positive");
+        return KC_EINVAL;
+    }
+    return factorize_impl(f, x_dev, kernel.nu, kernel.lengthscale, nullptr, pivot, tau, count_updates, stream);
+}
+
+kc_status kc_factorize_batched(kc_factor* f, const double* x_dev, double nu, const double* ell_dev, kc_pivot pivot,
+                               double tau, int32_t count_updates, void* stream) {
+    if (!f || !x_dev || !ell_dev) return KC_EINVAL;
+    if (f->ninst < 2) {
+        kc::set_error("kc_factorize_batched: the plan holds a single problem; use kc_factorize");
+        return KC_EINVAL;
+    }
+    return factorize_impl(f, x_dev, nu, 0.0, ell_dev, pivot, tau, count_updates, stream);
 }
 
 kc_status kc_theta(kc_factor* f, const double* x_dev, kc_kernel kernel, double* theta_dev, void* stream) {
@@ -991,5 +1092,103 @@ kc_status kc_factor_export_L(const kc_factor* f, double* vals) {
 }
 
 void kc_factor_destroy(kc_factor* f) { delete f; }
+
+kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double ell, const double* ell_dev,
+                         kc_pivot pivot, double tau, int32_t reps, void* stream, int32_t* chosen_wpb) {
+    if (!f || !x_dev || reps < 1) return KC_EINVAL;
+    if ((f->ninst > 1) != (ell_dev != nullptr)) {
+        kc::set_error("kc_factor_tune: pass ell_dev exactly for batch plans");
+        return KC_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t vt = f->prec == KC_FP64 ? sizeof(double) : sizeof(float);
+    hipEvent_t a = nullptr, b = nullptr;
+    KC_HIP(hipEventCreate(&a));
+    KC_HIP(hipEventCreate(&b));
+    int best = f->wpb;
+    float best_ms = 1e30f;
+    for (int wpb : {1, 2, 4}) {
+        if (size_t(wpb) * f->cap * (vt + 4) > 64 * 1024) continue;
+        f->wpb = wpb;
+        kc_status st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, stream);  // warm-up
+        if (st != KC_OK) break;
+        KC_HIP(hipEventRecord(a, s));
+        for (int r = 0; r < reps && st == KC_OK; ++r) st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, stream);
+        KC_HIP(hipEventRecord(b, s));
+        KC_HIP(hipEventSynchronize(b));
+        if (st != KC_OK) break;
+        float ms = 0.f;
+        KC_HIP(hipEventElapsedTime(&ms, a, b));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = wpb;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    f->wpb = best;
+    if (chosen_wpb) *chosen_wpb = best;
+    return KC_OK;
+}
+
+struct kc_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~kc_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+kc_status kc_graph_create(kc_factor* f, const double* x_dev, double nu, double ell, const double* ell_dev,
+                          kc_pivot pivot, double tau, const double* b_dev, double* sol_dev, int32_t nrhs,
+                          void* scratch_dev, size_t scratch_bytes, kc_graph** out) {
+    if (!out || !f || !x_dev || !b_dev || !sol_dev || !scratch_dev || nrhs < 1) return KC_EINVAL;
+    *out = nullptr;
+    if ((f->ninst > 1) != (ell_dev != nullptr)) {
+        kc::set_error("kc_graph_create: pass ell_dev exactly for batch plans");
+        return KC_EINVAL;
+    }
+    if (scratch_bytes < solve_scratch_bytes(f, nrhs) || reinterpret_cast<uintptr_t>(scratch_dev) % 256) {
+        kc::set_error("kc_graph_create: scratch must be 256-byte aligned and hold kc_solve_bytes bytes");
+        return KC_EWORKSPACE;
+    }
+    std::unique_ptr<kc_graph> g(new (std::nothrow) kc_graph);
+    if (!g) return KC_ENOMEM;
+    hipStream_t cs = nullptr;
+    KC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    kc_status st = KC_OK;
+    if (e == hipSuccess) {
+        st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, cs);
+        if (st == KC_OK) {
+            double* y = static_cast<double*>(scratch_dev);
+            double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
+                                                        align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
+            st = f->prec == KC_FP64 ? solve_typed<double>(f, b_dev, sol_dev, nrhs, y, partial, cs)
+                                    : solve_typed<float>(f, b_dev, sol_dev, nrhs, y, partial, cs);
+        }
+        hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+        if (e2 != hipSuccess && st == KC_OK) e = e2;
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        kc::set_error(std::string("kc_graph_create: capture failed: ") + hipGetErrorString(e));
+        return KC_EHIP;
+    }
+    if (st != KC_OK) return st;
+    KC_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    f->factorized = true;
+    *out = g.release();
+    return KC_OK;
+}
+
+kc_status kc_graph_launch(kc_graph* g, void* stream) {
+    if (!g) return KC_EINVAL;
+    KC_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return KC_OK;
+}
+
+void kc_graph_destroy(kc_graph* g) { delete g; }
 
 }  // extern "C"

@@ -65,6 +65,11 @@ struct Plan {
     std::vector<int32_t> bwd_cols;  // columns grouped by reverse level
     std::vector<int64_t> bwd_off;   // nrlevels + 1
 
+    // independent instances (a batch): positions [inst_off[i], inst_off[i+1]) belong to instance i
+    int32_t ninst = 1;
+    std::vector<int64_t> inst_off;  // ninst + 1
+    std::vector<int32_t> inst;      // instance of each position (empty for a single instance)
+
     int64_t max_col = 0, max_row = 0;
     double t_order = 0, t_pattern = 0, t_schedule = 0;
 
@@ -76,6 +81,8 @@ struct Plan {
 void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t* perm, double* l);
 void build_pattern(Plan& p, int nthreads);
 void build_schedule(Plan& p, int nthreads);
+// Block-diagonal union of independently analysed instances.
+void merge_plans(const std::vector<Plan>& parts, Plan& out);
 
 // Thread-local error message shared by the C ABI.
 void set_error(const std::string& msg);

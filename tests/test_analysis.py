@@ -70,3 +70,25 @@ def test_full_size_pattern_matches_paper(golden):
     g = golden["vary_rho_1e6_2d"]
     p = K.analyze(W.uniform_points(g["N"], 2, 14), 3.0)
     assert p.nnz / g["N"] ** 2 == pytest.approx(g["nnz_over_N2"][1], rel=0.03)
+
+
+def test_batched_plan_is_the_union_of_instances():
+    xs = [W.uniform_points(n, 2, 30 + i) for i, n in enumerate([300, 1, 50, 700, 2])]
+    pb = K.analyze_batched(xs, 3.0)
+    assert pb.info()["ninst"] == len(xs)
+    perm, l, cp, ri = pb.export()
+    lv = pb.levels()
+    off = eo = 0
+    depth = 0
+    for x in xs:
+        P = O.pattern(x, 3.0)
+        n = len(x)
+        np.testing.assert_array_equal(perm[off:off + n] - off, P.perm)
+        np.testing.assert_array_equal(l[off:off + n], P.l)
+        np.testing.assert_array_equal(cp[off:off + n + 1] - eo, P.colptr)
+        np.testing.assert_array_equal(ri[eo:eo + P.nnz] - off, P.rowidx)
+        np.testing.assert_array_equal(lv[off:off + n], K.analyze(x, 3.0).levels())
+        depth = max(depth, K.analyze(x, 3.0).info()["nlevels"])
+        off += n
+        eo += P.nnz
+    assert pb.info()["nlevels"] == depth

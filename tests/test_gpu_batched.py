@@ -1,0 +1,124 @@
+"""Many independent problems in one level-launch sequence: parity per instance,
+HIP-graph replays, and the autotuner's choice (which must not change results)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1706_02205_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1706_02205_amd as K
+    return K
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def batch():
+    # the batched recipe shrunk so the oracle finishes quickly: N log-uniform in [40, 2000]
+    inst = W.batched_instances(24, 40, 2000, seed=4100)
+    xs = [b.points for b in inst]
+    ells = np.array([b.lengthscale for b in inst])
+    ref = []
+    for x, ell in zip(xs, ells):
+        P = O.pattern(x, 3.0)
+        ref.append((P, O.ichol(P, O.theta_on_pattern(P, 1.5, ell))))
+    b = np.concatenate([W.gaussian_rhs(len(x), 1, 4200 + i) for i, x in enumerate(xs)])
+    return xs, ells, ref, b
+
+
+def run_batch(K, xs, ells, prec="fp64", pivot="zero", tau=0.0):
+    plan = K.analyze_batched(xs, 3.0)
+    f = K.Factor(plan, prec)
+    xd = dev(np.concatenate(xs))
+    ed = dev(ells)
+    f.factorize_batched(xd, 1.5, ed, pivot, tau, count_updates=True)
+    return plan, f, xd, ed
+
+
+def test_batched_factor_and_solve_bitwise_per_instance(K, batch):
+    print("[gpu] batched parity", flush=True)
+    xs, ells, ref, b = batch
+    plan, f, xd, ed = run_batch(K, xs, ells)
+    L = f.export_L()
+    st = f.stats()
+    sol = f.solve(dev(b)).cpu().numpy()
+    assert st.nonpositive == sum(R.nonpositive for _, R in ref)
+    assert st.updates == sum(R.updates for _, R in ref)
+    e0 = o0 = 0
+    for x, (P, R) in zip(xs, ref):
+        assert np.array_equal(L[e0:e0 + P.nnz], R.L)
+        assert np.array_equal(sol[o0:o0 + P.n], O.solve(P, R.L, b[o0:o0 + P.n]))
+        e0 += P.nnz
+        o0 += P.n
+
+
+def test_graph_replays_match_eager(K, batch):
+    print("[gpu] batched graph replays", flush=True)
+    import torch
+    xs, ells, ref, b = batch
+    plan, f, xd, ed = run_batch(K, xs, ells)
+    bd = dev(b)
+    eager = f.solve(bd).cpu().numpy()
+    eager_L = f.export_L()
+    g = f.capture(xd, bd, 1.5, ell_dev=ed)
+    for rep in range(3):
+        out = g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), f"replay {rep}"
+        assert np.array_equal(f.export_L(), eager_L)
+        # eager work between replays
+        f.factorize_batched(xd, 1.5, ed)
+        assert np.array_equal(f.solve(bd).cpu().numpy(), eager)
+
+
+def test_tuner_choice_does_not_change_results(K, batch):
+    print("[gpu] autotuner", flush=True)
+    xs, ells, ref, b = batch
+    plan, f, xd, ed = run_batch(K, xs, ells)
+    base = f.export_L()
+    wpb = f.tune(xd, 1.5, ell_dev=ed, reps=2)
+    assert wpb in (1, 2, 4)
+    f.factorize_batched(xd, 1.5, ed)
+    assert np.array_equal(f.export_L(), base)
+
+
+def test_single_problem_graph(K):
+    print("[gpu] single-problem graph", flush=True)
+    import torch
+    w = W.small_uniform_2d()
+    plan = K.analyze(w.points, w.rho)
+    f = K.Factor(plan, "mixed")
+    xd, bd = dev(w.points), dev(w.rhs())
+    f.factorize(xd, w.nu, w.lengthscale, "shift", 1e-6)
+    eager = f.solve(bd).cpu().numpy()
+    g = f.capture(xd, bd, w.nu, w.lengthscale, pivot="shift", tau=1e-6)
+    for _ in range(3):
+        out = g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager)
+
+
+def test_batched_mixed_error(K, batch):
+    print("[gpu] batched mixed", flush=True)
+    xs, ells, ref, b = batch
+    plan, f, xd, ed = run_batch(K, xs, ells, "mixed", "shift", 1e-6)
+    L = f.export_L()
+    e0 = 0
+    worst = 0.0
+    for P, R in ref:
+        if R.nonpositive == 0:
+            worst = max(worst, np.linalg.norm(L[e0:e0 + P.nnz] - R.L) / np.linalg.norm(R.L))
+        e0 += P.nnz
+    print(f"[gpu] batched mixed: worst ||dL||/||L|| over instances without zeroed columns {worst:.2e}", flush=True)
+    assert worst < 1e-3
