@@ -180,6 +180,31 @@ def run_batched(args):
         "updates": st.updates, "host_analysis_s": t_analysis}), flush=True)
 
 
+def run_serving(args):
+    """Poisson arrivals of factor+solve requests: N log-uniform in [1e3, 2e5], points of intrinsic
+    dimension 2 in R^20, Matern-3/2 l=0.2, rho=3, 4 right-hand sides, mixed precision, factors kept
+    resident within a 64 GB nnz(S)-proportional budget.  Reports p50/p99 latency and throughput."""
+    from paper_1706_02205_amd import serve
+    from paper_1706_02205_amd import workloads as W
+    reqs = W.serving_trace(args.requests, args.rate)
+    trace = [(r.arrival_s, r.points, W.gaussian_rhs(len(r.points), 4, r.rhs_seed)) for r in reqs]
+    srv = serve.Server(1.5, 0.2, 3.0, prec="mixed", budget_bytes=64e9, max_inflight=16, nstreams=4,
+                       analysis_threads=args.analysis_threads)
+    st = srv.run(trace)
+    srv.close()
+    s = st.summary()
+    log(f"[bench] serving: {s}")
+    print(json.dumps({
+        "metric": "serve p50/p99 ms", "value": s["p50_ms"], "unit": "ms", "n_gpus": 1, "steps": len(trace),
+        "warmup": 0, "ms_per_step": s["mean_ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-updates/f64-pivots", "data": "synthetic",
+        "config": {"workload": f"serve-sincos20d-{len(trace)}req-rate{args.rate:g}", "rate_per_s": args.rate,
+                   "n_range": [1000, 200000], "nrhs": 4, "budget_bytes": 64e9},
+        "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "throughput_req_s": s["throughput_req_s"],
+        "s_entries_per_s": s["s_entries_per_s"], "peak_inflight": s["peak_inflight"],
+        "peak_resident_bytes": s["peak_resident_bytes"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,8 +219,12 @@ def main():
                     help="also time CG on the dense Theta to this residual with each factor (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
-    ap.add_argument("--workload", default="grid", choices=["grid", "batched"],
-                    help="grid: the 10^6-point benchmark (default); batched: 512 independent instances")
+    ap.add_argument("--workload", default="grid", choices=["grid", "batched", "serve"],
+                    help="grid: the 10^6-point benchmark (default); batched: 512 independent instances; "
+                         "serve: Poisson trace of factor+solve requests")
+    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--rate", type=float, default=4.0, help="serving arrival rate (requests/s)")
+    ap.add_argument("--analysis-threads", type=int, default=12)
     ap.add_argument("--instances", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -205,6 +234,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "serve":
+        run_serving(args)
         return
 
     import paper_1706_02205_amd as K

@@ -251,28 +251,120 @@ void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t*
 
 namespace {
 
-void csr_from_csc(Plan& p) {
-    // rows start on multiples of kRowAlign entries and are padded with INT32_MAX
+void csr_from_csc(Plan& p, int nthreads) {
+    // Rows start on multiples of kRowAlign entries and are padded with INT32_MAX.
+    // Threads own balanced ranges of columns; a row's entries from thread t are
+    // placed after those of threads t' < t, so rows stay sorted by column.
     const int64_t n = p.n, nnz = p.nnz();
-    std::vector<int64_t> len(size_t(n), 0);
-    for (int64_t e = 0; e < nnz; ++e) len[size_t(p.rowidx[e])]++;
+    const int T = std::max(1, std::min<int>(nthreads, int(std::max<int64_t>(1, nnz / 4096))));
+    std::vector<int64_t> cut(size_t(T + 1), n);
+    cut[0] = 0;
+    for (int t = 1; t < T; ++t)
+        cut[t] = std::lower_bound(p.colptr.begin(), p.colptr.end(), nnz * t / T) - p.colptr.begin();
+    for (int t = 1; t <= T; ++t) cut[t] = std::max(cut[t], cut[t - 1]);
+    std::vector<std::vector<int64_t>> base(static_cast<size_t>(T));
+    parallel_for(T, T, 1, [&](int64_t t0, int64_t t1, int) {
+        for (int64_t t = t0; t < t1; ++t) {
+            std::vector<int64_t>& c = base[size_t(t)];
+            c.assign(size_t(n), 0);
+            for (int64_t e = p.colptr[cut[t]]; e < p.colptr[cut[t + 1]]; ++e) c[size_t(p.rowidx[e])]++;
+        }
+    });
+    std::vector<int64_t> len(static_cast<size_t>(n), 0);
+    parallel_for(T, n, 1 << 16, [&](int64_t k0, int64_t k1, int) {
+        for (int64_t k = k0; k < k1; ++k) {
+            int64_t acc = 0;
+            for (int t = 0; t < T; ++t) {
+                const int64_t c = base[size_t(t)][size_t(k)];
+                base[size_t(t)][size_t(k)] = acc;  // offset of thread t's entries inside row k
+                acc += c;
+            }
+            len[size_t(k)] = acc;
+        }
+    });
     p.rowptr.assign(size_t(n + 1), 0);
     p.rowend.resize(size_t(n));
+    p.max_row = 0;
     for (int64_t k = 0; k < n; ++k) {
         p.rowend[k] = p.rowptr[k] + len[k];
         p.rowptr[k + 1] = p.rowptr[k] + (len[k] + kRowAlign - 1) / kRowAlign * kRowAlign;
+        p.max_row = std::max(p.max_row, len[k]);
     }
     p.colidx.assign(size_t(p.rowptr[n]), INT32_MAX);
     p.csc2csr.resize(size_t(nnz));
-    std::vector<int64_t> fill(p.rowptr.begin(), p.rowptr.end() - 1);
-    for (int64_t j = 0; j < n; ++j)
-        for (int64_t e = p.colptr[j]; e < p.colptr[j + 1]; ++e) {
-            int64_t q = fill[size_t(p.rowidx[e])]++;
-            p.colidx[size_t(q)] = int32_t(j);
-            p.csc2csr[size_t(e)] = uint32_t(q);
+    parallel_for(T, T, 1, [&](int64_t t0, int64_t t1, int) {
+        for (int64_t t = t0; t < t1; ++t) {
+            std::vector<int64_t>& off = base[size_t(t)];
+            for (int64_t j = cut[t]; j < cut[t + 1]; ++j)
+                for (int64_t e = p.colptr[j]; e < p.colptr[j + 1]; ++e) {
+                    const int64_t k = p.rowidx[e];
+                    const int64_t q = p.rowptr[k] + off[size_t(k)]++;
+                    p.colidx[size_t(q)] = int32_t(j);
+                    p.csc2csr[size_t(e)] = uint32_t(q);
+                }
         }
-    p.max_row = 0;
-    for (int64_t k = 0; k < n; ++k) p.max_row = std::max(p.max_row, len[k]);
+    });
+}
+
+}  // namespace
+
+namespace {
+
+// dist(a,b) <= R with the canonical expression.  The running sum of squares is
+// the canonical one and only grows, so once it exceeds R2 -- an upper bound on
+// every s with sqrt(s) <= R after rounding -- the point cannot be within R.
+inline bool within(const double* a, const double* b, int d, double R, double R2) {
+    double s = 0.0;
+    for (int t = 0; t < d; ++t) {
+        double df = a[t] - b[t];
+        s += df * df;
+        if (s > R2) return false;
+    }
+    return std::sqrt(s) <= R;
+}
+
+inline double r2_bound(double R) { return R * R * (1.0 + 1e-12) + 1e-300; }
+
+// Runs scan(i, buf) for i in [0, n) on parallel chunks; scan appends item i's
+// values to buf.  The values are concatenated in order of i into vals, with
+// offsets ptr (n + 1).  One pass: each chunk's values stay in the buffer of the
+// thread that produced them until the final copy.
+template <class Scan>
+void collect(int nthreads, int64_t n, Scan&& scan, std::vector<int64_t>& ptr, std::vector<int32_t>& vals) {
+    // The first items (the coarsest columns, whose balls cover most points) get a
+    // chunk each so that no thread is left with all the heavy ones.
+    constexpr int64_t kHeavy = 4096, kChunkItems = 64;
+    const int64_t nheavy = std::min(n, kHeavy);
+    const int64_t nchunks = nheavy + (n - nheavy + kChunkItems - 1) / kChunkItems;
+    auto chunk_begin = [&](int64_t c) { return c < nheavy ? c : nheavy + (c - nheavy) * kChunkItems; };
+    nthreads = std::max(1, nthreads);
+    std::vector<std::vector<int32_t>> bufs(static_cast<size_t>(nthreads));
+    std::vector<int32_t> chunk_thread(static_cast<size_t>(nchunks));
+    std::vector<int64_t> chunk_off(static_cast<size_t>(nchunks));
+    std::vector<int64_t> cnt(static_cast<size_t>(n), 0);
+    parallel_for(nthreads, nchunks, 1, [&](int64_t c0, int64_t c1, int tid) {
+        std::vector<int32_t>& buf = bufs[size_t(tid)];
+        for (int64_t c = c0; c < c1; ++c) {
+            chunk_thread[size_t(c)] = tid;
+            chunk_off[size_t(c)] = int64_t(buf.size());
+            const int64_t i1 = std::min(n, chunk_begin(c + 1));
+            for (int64_t i = chunk_begin(c); i < i1; ++i) {
+                const size_t before = buf.size();
+                scan(i, buf);
+                cnt[size_t(i)] = int64_t(buf.size() - before);
+            }
+        }
+    });
+    ptr.assign(size_t(n + 1), 0);
+    for (int64_t i = 0; i < n; ++i) ptr[size_t(i + 1)] = ptr[size_t(i)] + cnt[size_t(i)];
+    vals.resize(size_t(ptr[size_t(n)]));
+    parallel_for(nthreads, nchunks, 16, [&](int64_t c0, int64_t c1, int) {
+        for (int64_t c = c0; c < c1; ++c) {
+            const int64_t i0 = chunk_begin(c), i1 = std::min(n, chunk_begin(c + 1));
+            const int32_t* src = bufs[size_t(chunk_thread[size_t(c)])].data() + chunk_off[size_t(c)];
+            std::copy(src, src + (ptr[size_t(i1)] - ptr[size_t(i0)]), vals.data() + ptr[size_t(i0)]);
+        }
+    });
 }
 
 }  // namespace
@@ -285,73 +377,39 @@ void build_pattern(Plan& p, int nthreads) {
     KDTree tree;
     tree.build(xh, n, d);
     p.spatial = tree.idx;  // k-d tree leaf order: positions grouped by region
-    std::vector<int64_t> cnt(size_t(n), 0);
 
     if (p.rule == KC_RULE_MAX) {
-        // column b: rows a > b with dist(x_a, x_b) <= rho * max(l_a, l_b) = rho * l_b
-        auto scan = [&](int64_t b, auto&& emit) {
+        // column b: the diagonal, then rows a > b with dist(x_a, x_b) <= rho * max(l_a, l_b) = rho * l_b
+        collect(nthreads, n, [&](int64_t b, std::vector<int32_t>& out) {
             const double* xb = xh + size_t(b) * d;
-            double R = p.rho * p.l[size_t(b)];
+            const double R = p.rho * p.l[size_t(b)], R2 = r2_bound(R);
+            out.push_back(int32_t(b));
+            const size_t first = out.size();
             tree.visit(xb, R, int32_t(b + 1), int32_t(n - 1), [&](int32_t s, int32_t e) {
                 for (int32_t t = s; t < e; ++t) {
-                    int32_t a = tree.idx[t];
-                    if (a > b && dist(xh + size_t(a) * d, xb, d) <= R) emit(a);
+                    const int32_t a = tree.idx[t];
+                    if (a > b && within(xh + size_t(a) * d, xb, d, R, R2)) out.push_back(a);
                 }
             });
-        };
-        parallel_for(nthreads, n, 64, [&](int64_t b0, int64_t b1, int) {
-            for (int64_t b = b0; b < b1; ++b) {
-                int64_t c = 1;
-                scan(b, [&](int32_t) { ++c; });
-                cnt[b] = c;
-            }
-        });
-        p.colptr.assign(size_t(n + 1), 0);
-        for (int64_t b = 0; b < n; ++b) p.colptr[b + 1] = p.colptr[b] + cnt[b];
-        if (p.colptr[n] >= (int64_t(1) << 32)) return;  // caller reports KC_ERANGE
-        p.rowidx.resize(size_t(p.colptr[n]));
-        parallel_for(nthreads, n, 64, [&](int64_t b0, int64_t b1, int) {
-            for (int64_t b = b0; b < b1; ++b) {
-                int32_t* out = p.rowidx.data() + p.colptr[b];
-                int64_t c = 0;
-                out[c++] = int32_t(b);
-                scan(b, [&](int32_t a) { out[c++] = a; });
-                std::sort(out + 1, out + c);
-            }
-        });
+            std::sort(out.begin() + first, out.end());
+        }, p.colptr, p.rowidx);
     } else {
         // row a: columns b < a with dist(x_a, x_b) <= rho * min(l_a, l_b) = rho * l_a
-        std::vector<int64_t> rcnt(size_t(n), 0);
-        auto scan = [&](int64_t a, auto&& emit) {
+        std::vector<int64_t> rp;
+        std::vector<int32_t> cols;
+        collect(nthreads, n, [&](int64_t a, std::vector<int32_t>& out) {
             const double* xa = xh + size_t(a) * d;
-            double R = p.rho * p.l[size_t(a)];
+            const double R = p.rho * p.l[size_t(a)], R2 = r2_bound(R);
             tree.visit(xa, R, 0, int32_t(a - 1), [&](int32_t s, int32_t e) {
                 for (int32_t t = s; t < e; ++t) {
-                    int32_t b = tree.idx[t];
-                    if (b < a && dist(xa, xh + size_t(b) * d, d) <= R) emit(b);
+                    const int32_t b = tree.idx[t];
+                    if (b < a && within(xa, xh + size_t(b) * d, d, R, R2)) out.push_back(b);
                 }
             });
-        };
-        parallel_for(nthreads, n, 64, [&](int64_t a0, int64_t a1, int) {
-            for (int64_t a = a0; a < a1; ++a) {
-                int64_t c = 0;
-                scan(a, [&](int32_t) { ++c; });
-                rcnt[a] = c;
-            }
-        });
-        std::vector<int64_t> rp(size_t(n + 1), 0);
-        for (int64_t a = 0; a < n; ++a) rp[a + 1] = rp[a] + rcnt[a];
-        std::vector<int32_t> cols(size_t(rp[n]));
-        parallel_for(nthreads, n, 64, [&](int64_t a0, int64_t a1, int) {
-            for (int64_t a = a0; a < a1; ++a) {
-                int32_t* out = cols.data() + rp[a];
-                int64_t c = 0;
-                scan(a, [&](int32_t b) { out[c++] = b; });
-            }
-        });
+        }, rp, cols);
         // transpose rows into CSC columns (diagonal first, rows ascending)
-        for (int64_t a = 0; a < n; ++a) cnt[a] = 1;
-        for (int32_t b : cols) cnt[b]++;
+        std::vector<int64_t> cnt(static_cast<size_t>(n), 1);
+        for (int32_t b : cols) cnt[size_t(b)]++;
         p.colptr.assign(size_t(n + 1), 0);
         for (int64_t b = 0; b < n; ++b) p.colptr[b + 1] = p.colptr[b] + cnt[b];
         if (p.colptr[n] >= (int64_t(1) << 32)) return;
@@ -361,9 +419,10 @@ void build_pattern(Plan& p, int nthreads) {
         for (int64_t a = 0; a < n; ++a)
             for (int64_t q = rp[a]; q < rp[a + 1]; ++q) p.rowidx[size_t(fill[cols[q]]++)] = int32_t(a);
     }
+    if (p.colptr[n] >= (int64_t(1) << 32)) return;  // caller reports KC_ERANGE
     p.max_col = 0;
     for (int64_t b = 0; b < n; ++b) p.max_col = std::max(p.max_col, p.colptr[b + 1] - p.colptr[b]);
-    csr_from_csc(p);
+    csr_from_csc(p, nthreads);
 }
 
 void build_schedule(Plan& p, int nthreads) {
