@@ -115,6 +115,20 @@ kc_status kc_analyze(const double *x, int64_t n, int32_t d, double rho, kc_rule 
  * factors every instance at that depth.  Instances run on separate host threads. */
 kc_status kc_analyze_batched(const double *x, const int64_t *counts, int32_t ninst, int32_t d, double rho,
                              kc_rule rule, int32_t nthreads, kc_plan **out);
+/* Supernodal ordering and pattern (the supernodal construction of the paper's
+ * stability analysis, Section 5): after the maximin ordering and the max-rule
+ * pattern S_rho, points are aggregated greedily in maximin order -- an
+ * unassigned point k starts a supernode and claims every later unassigned point
+ * a with l_a >= l_k/2 within 0.5*rho*l_k -- supernodes are ordered by their
+ * first point with members consecutive, and the pattern becomes the block
+ * closure: every member pair of supernodes with an S_rho pair between them.
+ * Its ICHOL(0) is the supernodal incomplete Cholesky factorization (dense
+ * blocks).  kc_plan_export reports the new ordering and pattern. */
+kc_status kc_analyze_supernodal(const double *x, int64_t n, int32_t d, double rho, int32_t nthreads,
+                                kc_plan **out);
+/* Supernode boundaries of a supernodal plan in positions (nsuper + 1 entries,
+ * snode_ptr may be NULL to query nsuper); nsuper = 0 for other plans. */
+kc_status kc_plan_supernodes(const kc_plan *plan, int64_t *snode_ptr, int64_t *nsuper);
 kc_status kc_plan_info(const kc_plan *plan, kc_plan_info_t *info);
 /* Copies the ordering and pattern into caller buffers (any may be NULL):
  * perm[N] (maximin position -> original index), l[N], colptr[N+1],

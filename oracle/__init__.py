@@ -65,6 +65,8 @@ def lib():
         L.or_ichol_leading.argtypes = [I64, _i64p, _i32p, I64, _f64p, I32, F64, _f64p]
         L.or_dense_matvec.argtypes = [_f64p, I64, I32, F64, F64, _f64p, I32, _f64p]
         L.or_dense_matvec_rows.argtypes = [_f64p, I64, I32, F64, F64, _f64p, I32, I64, _i64p, _f64p]
+        L.or_supernodes.argtypes = [_f64p, I64, I32, _f64p, F64, _i32p]
+        L.or_supernodes.restype = C.c_int64
         for fn in ("or_maximin", "or_pattern_count", "or_pattern_fill", "or_matern", "or_theta", "or_ichol",
                    "or_solve", "or_llt_pairs", "or_frob_error", "or_num_threads", "or_prefix_min_dist",
                    "or_theta_pairs", "or_ichol_leading", "or_dense_matvec", "or_dense_matvec_rows"):
@@ -320,3 +322,73 @@ def pcg(P: Pattern, L: np.ndarray, x: np.ndarray, nu: float, ell: float, b: np.n
         p = np.where(active, z + (rz_new / rz) * p, p)
         rz = rz_new
     return (sol[:, 0] if b.ndim == 1 else sol), it
+
+
+# --------------------------------------------------------------------------
+# Supernodal ordering and pattern (Section 5, supernodal construction used for
+# the stability proof; its incomplete factorization is the block algorithm of
+# the same section's appendix).
+
+def supernodal_pattern(x: np.ndarray, rho: float) -> "tuple[Pattern, np.ndarray]":
+    """Supernodal ordering + block-closed pattern, built from the brute-force maximin
+    ordering and pattern.  Returns (pattern in the new positions, supernode boundaries)."""
+    P = pattern(x, rho, RULE_MAX)
+    n, d = P.xh.shape
+    node = np.empty(n, np.int32)
+    ns = int(lib().or_supernodes(P.xh, n, d, P.l, float(rho), node))
+    # new order: supernodes by their first point, members in maximin order (stable sort)
+    order = np.argsort(node, kind="stable")
+    sptr = np.concatenate([[0], np.cumsum(np.bincount(node, minlength=ns))]).astype(np.int64)
+    # adjacency of supernodes: some member pair in S_rho
+    cols = np.repeat(np.arange(n), np.diff(P.colptr))
+    a, b = node[P.rowidx], node[cols]
+    adj = set(zip(np.maximum(a, b).tolist(), np.minimum(a, b).tolist()))
+    by_col = {}
+    for hi, lo in adj:
+        by_col.setdefault(lo, []).append(hi)
+    colptr = [0]
+    rows = []
+    for s in range(ns):
+        below = sorted(t for t in by_col.get(s, []) if t > s)
+        for q in range(sptr[s], sptr[s + 1]):
+            rows.extend(range(q, sptr[s + 1]))
+            for t in below:
+                rows.extend(range(sptr[t], sptr[t + 1]))
+            colptr.append(len(rows))
+    perm = P.perm[order]
+    Pn = Pattern(perm=perm.astype(np.int32), l=P.l[order], colptr=np.array(colptr, np.int64),
+                 rowidx=np.array(rows, np.int32), xh=np.ascontiguousarray(P.xh[order]))
+    return Pn, sptr
+
+
+def block_ichol(Pn: Pattern, sptr: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """Supernodal incomplete Cholesky in block form: for each supernode I in order,
+    L_{:,I} = K_{:,I} chol(K_{I,I})^{-T}; then K_{K,J} -= K_{K,I} K_{I,I}^{-1} K_{J,I}^T for
+    supernodes J >= I and K >= J adjacent to I with (K, J) adjacent.  Dense numpy, small n only."""
+    n = Pn.n
+    A = dense_from_csc(Pn, theta)
+    A = np.tril(A) + np.tril(A, -1).T
+    mask = dense_from_csc(Pn, np.ones(Pn.nnz)) != 0
+    mask = mask | mask.T
+    ns = len(sptr) - 1
+    L = np.zeros((n, n))
+    blocks = [slice(sptr[s], sptr[s + 1]) for s in range(ns)]
+    adj = np.zeros((ns, ns), bool)
+    for s in range(ns):
+        for t in range(ns):
+            adj[s, t] = mask[sptr[s], sptr[t]]
+    for i, I in enumerate(blocks):
+        C = np.linalg.cholesky(A[I, I])
+        rest = slice(sptr[i], n)
+        Li = np.linalg.solve(C, A[rest, I].T).T  # K_{:,I} C^{-T}
+        Li[:, :] *= mask[rest, I]
+        L[rest, I] = Li
+        kids = [t for t in range(i + 1, ns) if adj[t, i]]
+        for j in kids:
+            for k in kids:
+                if k >= j and adj[k, j]:
+                    Kb, Jb = blocks[k], blocks[j]
+                    A[Kb, Jb] -= L[Kb, I] @ L[Jb, I].T
+                    if k != j:
+                        A[Jb, Kb] = A[Kb, Jb].T
+    return L

@@ -481,3 +481,24 @@ int or_dense_matvec_rows(const double *x, int64_t n, int32_t d, double nu, doubl
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Supernodes (the supernodal construction of Section 5's stability analysis),
+ * brute force over maximin positions: greedily in maximin order, an unassigned
+ * point k starts supernode s and claims every later unassigned point a of the
+ * same scale (l_a >= l_k / 2) with dist(x_a, x_k) <= 0.5 * rho * l_k.
+ * node[k] receives the supernode of position k; returns the number of supernodes. */
+int64_t or_supernodes(const double *xh, int64_t n, int32_t d, const double *l, double rho, int32_t *node) {
+    for (int64_t k = 0; k < n; ++k) node[k] = -1;
+    int64_t ns = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        if (node[k] >= 0) continue;
+        node[k] = (int32_t)ns;
+        double R = 0.5 * rho * l[k], lmin = 0.5 * l[k];
+#pragma omp parallel for schedule(static)
+        for (int64_t a = k + 1; a < n; ++a)
+            if (node[a] < 0 && l[a] >= lmin && dist(xh + (size_t)a * d, xh + (size_t)k * d, d) <= R) node[a] = (int32_t)ns;
+        ++ns;
+    }
+    return ns;
+}

@@ -20,7 +20,7 @@ import numpy as np
 from . import _lib
 from ._lib import KCholError
 
-__all__ = ["analyze", "analyze_batched", "dense_matvec", "Plan", "Factor", "Graph", "KCholError"]
+__all__ = ["analyze", "analyze_supernodal", "analyze_batched", "dense_matvec", "Plan", "Factor", "Graph", "KCholError"]
 
 _RULES = {"max": _lib.KC_RULE_MAX, "min": _lib.KC_RULE_MIN}
 _PRECS = {"fp64": _lib.KC_FP64, "mixed": _lib.KC_MIXED}
@@ -69,6 +69,15 @@ class Plan:
                    "kc_plan_export")
         return perm, l, colptr, rowidx
 
+    def supernodes(self) -> np.ndarray:
+        """Supernode boundaries (positions) of a supernodal plan; empty for other plans."""
+        ns = C.c_int64()
+        _lib.check(_lib.load().kc_plan_supernodes(self._h, None, C.byref(ns)), "kc_plan_supernodes")
+        ptr = np.empty(ns.value + 1 if ns.value else 0, np.int64)
+        if ns.value:
+            _lib.check(_lib.load().kc_plan_supernodes(self._h, _ptr(ptr), C.byref(ns)), "kc_plan_supernodes")
+        return ptr
+
     def levels(self) -> np.ndarray:
         lv = np.empty(self.n, np.int32)
         _lib.check(_lib.load().kc_plan_levels(self._h, _ptr(lv)), "kc_plan_levels")
@@ -84,6 +93,18 @@ def analyze(x: np.ndarray, rho: float, rule: str = "max", nthreads: int = 0) -> 
     h = C.c_void_p()
     _lib.check(_lib.load().kc_analyze(_ptr(x), n, d, float(rho), _RULES[rule], int(nthreads), C.byref(h)),
                "kc_analyze")
+    return Plan(h, n, d)
+
+
+def analyze_supernodal(x: np.ndarray, rho: float, nthreads: int = 0) -> Plan:
+    """Supernodal ordering + block-closed pattern (aggregated maximin ordering) on the host."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("x must be (n, d)")
+    n, d = x.shape
+    h = C.c_void_p()
+    _lib.check(_lib.load().kc_analyze_supernodal(_ptr(x), n, d, float(rho), int(nthreads), C.byref(h)),
+               "kc_analyze_supernodal")
     return Plan(h, n, d)
 
 

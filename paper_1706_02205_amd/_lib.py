@@ -39,7 +39,8 @@ EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "
             "kc_plan_destroy", "kc_factor_bytes", "kc_factor_create", "kc_factorize", "kc_theta", "kc_solve_bytes",
             "kc_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
             "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
-            "kc_factor_tune", "kc_graph_create", "kc_graph_launch", "kc_graph_destroy")
+            "kc_factor_tune", "kc_graph_create", "kc_graph_launch", "kc_graph_destroy", "kc_analyze_supernodal",
+            "kc_plan_supernodes")
 
 _LIB = None
 
@@ -89,6 +90,8 @@ def load():
         "kc_graph_create": (C.c_int, [vp, vp, f64, f64, vp, C.c_int, f64, vp, vp, i32, vp, sz, P(vp)]),
         "kc_graph_launch": (C.c_int, [vp, vp]),
         "kc_graph_destroy": (None, [vp]),
+        "kc_analyze_supernodal": (C.c_int, [vp, i64, i32, f64, i32, P(vp)]),
+        "kc_plan_supernodes": (C.c_int, [vp, vp, P(i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -224,8 +224,8 @@ void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t*
     (void)nthreads;
     KDTree tree;
     tree.build(x, n, d);
-    std::vector<double> m(size_t(n), std::numeric_limits<double>::infinity());
-    std::vector<char> sel(size_t(n), 0);
+    std::vector<double> m(static_cast<size_t>(n), std::numeric_limits<double>::infinity());
+    std::vector<char> sel(static_cast<size_t>(n), 0);
     MaxHeap heap;
     heap.init(n, &m);
     for (int64_t k = 0; k < n; ++k) {
@@ -257,7 +257,7 @@ void csr_from_csc(Plan& p, int nthreads) {
     // placed after those of threads t' < t, so rows stay sorted by column.
     const int64_t n = p.n, nnz = p.nnz();
     const int T = std::max(1, std::min<int>(nthreads, int(std::max<int64_t>(1, nnz / 4096))));
-    std::vector<int64_t> cut(size_t(T + 1), n);
+    std::vector<int64_t> cut(static_cast<size_t>(T + 1), n);
     cut[0] = 0;
     for (int t = 1; t < T; ++t)
         cut[t] = std::lower_bound(p.colptr.begin(), p.colptr.end(), nnz * t / T) - p.colptr.begin();
@@ -440,7 +440,7 @@ void build_schedule(Plan& p, int nthreads) {
     int32_t nl = 0;
     for (int64_t j = 0; j < n; ++j) nl = std::max(nl, p.level[j] + 1);
     p.nlevels = nl;
-    std::vector<int64_t> loff(size_t(nl + 1), 0), uoff(size_t(nl + 1), 0);
+    std::vector<int64_t> loff(static_cast<size_t>(nl + 1), 0), uoff(size_t(nl + 1), 0);
     for (int64_t j = 0; j < n; ++j) {
         loff[size_t(p.level[j]) + 1]++;
         uoff[size_t(p.level[j]) + 1] += (p.colptr[j + 1] - p.colptr[j] + 63) / 64;
@@ -466,7 +466,7 @@ void build_schedule(Plan& p, int nthreads) {
         }
     }
     // reverse levels: column j after every k > j in column j
-    std::vector<int32_t> rl(size_t(n), 0);
+    std::vector<int32_t> rl(static_cast<size_t>(n), 0);
     int32_t nrl = 0;
     for (int64_t j = n - 1; j >= 0; --j) {
         int32_t v = 0;
@@ -596,6 +596,123 @@ void merge_plans(const std::vector<Plan>& parts, Plan& out) {
         out.t_pattern += p.t_pattern;
         out.t_schedule += p.t_schedule;
     }
+}
+
+}  // namespace kc
+
+namespace kc {
+
+// Supernodal ordering and sparsity pattern, after the construction in the
+// paper's stability analysis (Section 5, supernodal multicolor construction):
+//  * aggregation: greedily in maximin order, an unassigned point k starts a
+//    supernode and claims every later unassigned point a of the same scale
+//    (l_a >= l_k / 2) within 0.5 * rho * l_k;
+//  * ordering: supernodes by their first point, members consecutively in
+//    maximin order (the colouring is not needed: the level schedule of the
+//    elimination DAG provides the parallelism);
+//  * pattern: supernodes A and B are adjacent when some member pair is in the
+//    pattern S_rho; the new pattern contains every member pair of adjacent
+//    supernodes (the block closure), so the factor's nonzeros form dense blocks.
+void supernodal_transform(Plan& p, int nthreads) {
+    nthreads = resolve_threads(nthreads);
+    const int64_t n = p.n;
+    const int d = p.d;
+    const double* xh = p.xh.data();
+    // 1. aggregation
+    std::vector<int32_t> node(static_cast<size_t>(n), -1);
+    std::vector<int64_t> leader;
+    {
+        KDTree tree;
+        tree.build(xh, n, d);
+        for (int64_t k = 0; k < n; ++k) {
+            if (node[size_t(k)] >= 0) continue;
+            const int32_t s = int32_t(leader.size());
+            leader.push_back(k);
+            node[size_t(k)] = s;
+            const double R = 0.5 * p.rho * p.l[size_t(k)], R2 = r2_bound(R), lmin = 0.5 * p.l[size_t(k)];
+            const double* xk = xh + size_t(k) * d;
+            tree.visit(xk, R, int32_t(k + 1), int32_t(n - 1), [&](int32_t b, int32_t e) {
+                for (int32_t t = b; t < e; ++t) {
+                    const int32_t a = tree.idx[t];
+                    if (a > k && node[size_t(a)] < 0 && p.l[size_t(a)] >= lmin && within(xh + size_t(a) * d, xk, d, R, R2))
+                        node[size_t(a)] = s;
+                }
+            });
+        }
+    }
+    const int64_t ns = int64_t(leader.size());
+    // 2. new order: supernodes in order of their first point, members in maximin order
+    std::vector<int64_t> sptr(static_cast<size_t>(ns + 1), 0);
+    for (int64_t k = 0; k < n; ++k) sptr[size_t(node[size_t(k)]) + 1]++;
+    for (int64_t s = 0; s < ns; ++s) sptr[size_t(s + 1)] += sptr[size_t(s)];
+    std::vector<int64_t> newpos(static_cast<size_t>(n));
+    std::vector<int32_t> oldpos(static_cast<size_t>(n));
+    {
+        std::vector<int64_t> fill(sptr.begin(), sptr.end() - 1);
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t q = fill[size_t(node[size_t(k)])]++;
+            newpos[size_t(k)] = q;
+            oldpos[size_t(q)] = int32_t(k);
+        }
+    }
+    // 3. supernode adjacency (symmetric), kept for the larger supernode index of each pair
+    std::vector<std::vector<int32_t>> adj(static_cast<size_t>(ns));
+    parallel_for(nthreads, ns, 64, [&](int64_t s0, int64_t s1, int) {
+        std::vector<int64_t> stamp;
+        for (int64_t s = s0; s < s1; ++s) {
+            std::vector<int32_t>& out = adj[size_t(s)];
+            auto add = [&](int32_t t) {
+                if (t >= s) out.push_back(t);
+            };
+            for (int64_t q = sptr[size_t(s)]; q < sptr[size_t(s + 1)]; ++q) {
+                const int64_t c = oldpos[size_t(q)];
+                for (int64_t e = p.colptr[c]; e < p.colptr[c + 1]; ++e) add(node[size_t(p.rowidx[e])]);
+                for (int64_t e = p.rowptr[c]; e < p.rowend[c]; ++e) add(node[size_t(p.colidx[e])]);
+            }
+            std::sort(out.begin(), out.end());
+            out.erase(std::unique(out.begin(), out.end()), out.end());
+        }
+    });
+    // 4. block-closed pattern in the new positions
+    std::vector<int64_t> colptr(static_cast<size_t>(n + 1), 0);
+    for (int64_t s = 0; s < ns; ++s) {
+        int64_t below = 0;
+        for (int32_t t : adj[size_t(s)])
+            if (t > s) below += sptr[size_t(t + 1)] - sptr[size_t(t)];
+        for (int64_t q = sptr[size_t(s)]; q < sptr[size_t(s + 1)]; ++q) colptr[size_t(q + 1)] = below + (sptr[size_t(s + 1)] - q);
+    }
+    for (int64_t q = 0; q < n; ++q) colptr[size_t(q + 1)] += colptr[size_t(q)];
+    std::vector<int32_t> rowidx(size_t(colptr[size_t(n)]));
+    parallel_for(nthreads, ns, 64, [&](int64_t s0, int64_t s1, int) {
+        for (int64_t s = s0; s < s1; ++s)
+            for (int64_t q = sptr[size_t(s)]; q < sptr[size_t(s + 1)]; ++q) {
+                int64_t w = colptr[size_t(q)];
+                for (int64_t r = q; r < sptr[size_t(s + 1)]; ++r) rowidx[size_t(w++)] = int32_t(r);
+                for (int32_t t : adj[size_t(s)])
+                    if (t > s)
+                        for (int64_t r = sptr[size_t(t)]; r < sptr[size_t(t + 1)]; ++r) rowidx[size_t(w++)] = int32_t(r);
+            }
+    });
+    // 5. replace ordering, points and pattern
+    std::vector<int32_t> perm(static_cast<size_t>(n));
+    std::vector<double> l(static_cast<size_t>(n)), xn(size_t(n) * d);
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t k = oldpos[size_t(q)];
+        perm[size_t(q)] = p.perm[size_t(k)];
+        l[size_t(q)] = p.l[size_t(k)];
+        for (int t = 0; t < d; ++t) xn[size_t(q) * d + t] = xh[size_t(k) * d + t];
+    }
+    for (auto& v : p.spatial) v = int32_t(newpos[size_t(v)]);
+    p.perm.swap(perm);
+    p.l.swap(l);
+    p.xh.swap(xn);
+    p.colptr.swap(colptr);
+    p.rowidx.swap(rowidx);
+    p.snode_ptr.swap(sptr);
+    if (p.nnz() >= (int64_t(1) << 32)) return;
+    p.max_col = 0;
+    for (int64_t b = 0; b < n; ++b) p.max_col = std::max(p.max_col, p.colptr[b + 1] - p.colptr[b]);
+    csr_from_csc(p, nthreads);
 }
 
 }  // namespace kc

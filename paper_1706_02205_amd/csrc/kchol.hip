@@ -708,7 +708,7 @@ static kc_status check_points(const double* x, int64_t n, int32_t d, double rho,
 }
 
 static void analyze_one(const double* x, int64_t n, int32_t d, double rho, kc_rule rule, int32_t nthreads,
-                        kc::Plan& p) {
+                        kc::Plan& p, bool supernodal = false) {
     p.n = n;
     p.d = d;
     p.rho = rho;
@@ -722,6 +722,8 @@ static void analyze_one(const double* x, int64_t n, int32_t d, double rho, kc_ru
     for (int64_t k = 0; k < n; ++k)
         for (int t = 0; t < d; ++t) p.xh[size_t(k) * d + t] = x[size_t(p.perm[k]) * d + t];
     kc::build_pattern(p, nthreads);
+    if (supernodal && p.nnz() < (int64_t(1) << 32) && p.nnz_rows() < (int64_t(1) << 32))
+        kc::supernodal_transform(p, nthreads);
     auto t2 = std::chrono::steady_clock::now();
     if (p.nnz() < (int64_t(1) << 32) && p.nnz_rows() < (int64_t(1) << 32)) kc::build_schedule(p, nthreads);
     auto t3 = std::chrono::steady_clock::now();
@@ -754,6 +756,42 @@ kc_status kc_analyze(const double* x, int64_t n, int32_t d, double rho, kc_rule 
         return KC_ERANGE;
     }
     *out = plan;
+    return KC_OK;
+}
+
+kc_status kc_analyze_supernodal(const double* x, int64_t n, int32_t d, double rho, int32_t nthreads,
+                                kc_plan** out) {
+    if (!out) return KC_EINVAL;
+    *out = nullptr;
+    const kc_status st = check_points(x, n, d, rho, KC_RULE_MAX);
+    if (st != KC_OK) return st;
+    kc_plan* plan = new (std::nothrow) kc_plan;
+    if (!plan) return KC_ENOMEM;
+    try {
+        analyze_one(x, n, d, rho, KC_RULE_MAX, nthreads, plan->p, true);
+    } catch (const std::bad_alloc&) {
+        delete plan;
+        kc::set_error("kc_analyze_supernodal: out of host memory");
+        return KC_ENOMEM;
+    }
+    if (plan->p.nnz() >= (int64_t(1) << 32) || plan->p.nnz_rows() >= (int64_t(1) << 32)) {
+        delete plan;
+        kc::set_error("kc_analyze_supernodal: nnz(S) >= 2^32");
+        return KC_ERANGE;
+    }
+    *out = plan;
+    return KC_OK;
+}
+
+kc_status kc_plan_supernodes(const kc_plan* plan, int64_t* snode_ptr, int64_t* nsuper) {
+    if (!plan || !nsuper) return KC_EINVAL;
+    const kc::Plan& p = plan->p;
+    if (p.snode_ptr.empty()) {
+        *nsuper = 0;
+        return KC_OK;
+    }
+    *nsuper = int64_t(p.snode_ptr.size()) - 1;
+    if (snode_ptr) std::memcpy(snode_ptr, p.snode_ptr.data(), p.snode_ptr.size() * sizeof(int64_t));
     return KC_OK;
 }
 

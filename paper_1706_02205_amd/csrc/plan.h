@@ -65,6 +65,9 @@ struct Plan {
     std::vector<int32_t> bwd_cols;  // columns grouped by reverse level
     std::vector<int64_t> bwd_off;   // nrlevels + 1
 
+    // supernodes (supernodal plans only): positions [snode_ptr[s], snode_ptr[s+1]) form supernode s
+    std::vector<int64_t> snode_ptr;
+
     // independent instances (a batch): positions [inst_off[i], inst_off[i+1]) belong to instance i
     int32_t ninst = 1;
     std::vector<int64_t> inst_off;  // ninst + 1
@@ -81,6 +84,10 @@ struct Plan {
 void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t* perm, double* l);
 void build_pattern(Plan& p, int nthreads);
 void build_schedule(Plan& p, int nthreads);
+// Supernodal ordering and pattern (aggregation of nearby points of one scale):
+// turns a plan with the maximin ordering and plain pattern into one whose
+// positions list supernodes consecutively and whose pattern is the block closure.
+void supernodal_transform(Plan& p, int nthreads);
 // Block-diagonal union of independently analysed instances.
 void merge_plans(const std::vector<Plan>& parts, Plan& out);
 

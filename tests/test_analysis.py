@@ -92,3 +92,16 @@ def test_batched_plan_is_the_union_of_instances():
         off += n
         eo += P.nnz
     assert pb.info()["nlevels"] == depth
+
+
+@pytest.mark.parametrize("n,d,rho,seed", [(3000, 3, 3.0, 5), (2500, 2, 2.0, 6), (800, 5, 1.5, 7)])
+def test_supernodal_plan_matches_oracle(n, d, rho, seed):
+    x = W.uniform_points(n, d, seed)
+    Pn, sptr = O.supernodal_pattern(x, rho)
+    p = K.analyze_supernodal(x, rho)
+    perm, l, cp, ri = p.export()
+    np.testing.assert_array_equal(perm, Pn.perm)
+    np.testing.assert_array_equal(l, Pn.l)
+    np.testing.assert_array_equal(cp, Pn.colptr)
+    np.testing.assert_array_equal(ri, Pn.rowidx)
+    np.testing.assert_array_equal(p.supernodes(), sptr)
