@@ -22,8 +22,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-pthread", "-Wall", "-Wextra",
               "-Wno-unused-parameter"]
+# -amdgpu-mfma-vgpr-form: matrix-core accumulators live in ordinary VGPRs, so the
+# dense product's accumulators are not copied to and from AGPRs around each MFMA.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+             "-Wno-unused-command-line-argument"]
 
 
 def _run(cmd, verbose):

@@ -5,9 +5,9 @@
 // alone is not accurate enough).  Each iteration needs one product with the
 // dense N x N Theta, whose entries are generated on the fly: the work is N^2
 // evaluations of the kernel (a square root and an exponential each), bound by
-// the FP64 vector ALUs, not by memory and not by matrix cores -- there is no
-// reusable operand to contract.  Rows are owned by threads; columns stream
-// through LDS in tiles shared by the 256 rows of a block.
+// the FP64 vector ALUs, not by memory.  The generated values are contracted
+// with the right-hand sides on the matrix cores (FP64 MFMA), which leaves the
+// vector ALUs with the kernel evaluations alone.
 //
 // All reductions (dot products) use a fixed grid and a fixed combination order,
 // so results are reproducible run to run.
@@ -29,69 +29,175 @@ void set_error(const std::string& msg);
 namespace {
 
 constexpr int kRows = 256;       // rows (threads) per block
-constexpr int kTileJ = 256;      // columns staged per LDS tile
+constexpr int kTileJ = 256;      // columns staged per LDS tile (at most)
 constexpr int kDotBlocks = 512;  // fixed grid of the dot-product reduction
-constexpr int kMaxNr = 8;
 
+// exp(x) for -707 <= x <= 0 by table lookup and a short polynomial (Tang's
+// method, ACM TOMS 15(2), 1989): x = (256 m + j) ln2/256 + r with
+// |r| <= ln2/512, so exp(x) = 2^m 2^(j/256) exp(r).  2^(j/256) comes from a
+// 256-entry table in LDS, exp(r) - 1 from its degree-4 Taylor polynomial
+// (truncation below 4e-17).  On this range 2^m never leaves the normal
+// numbers, so it is applied by an integer add to the exponent field.
+constexpr int kExpBits = 8;
+constexpr int kExpSize = 1 << kExpBits;
+constexpr double kShift = 6755399441055744.0;          // 1.5 * 2^52: adding it rounds to an integer
+constexpr double kInvLn2xN = 369.32993046757463;       // 256 / ln 2 (only selects the reduction)
+constexpr double kLn2dNHi = 0.0027076061740622863;     // ln 2 / 256 rounded to double
+constexpr double kMaxArg = 707.0;                      // exp(-707) is still a normal number
+
+struct ExpTable {
+    double t[kExpSize];  // 2^(j/256)
+    double lo;           // ln 2 / 256 - kLn2dNHi
+};
+
+ExpTable make_exp_table() {
+    ExpTable e{};
+    for (int j = 0; j < kExpSize; ++j)
+        e.t[j] = static_cast<double>(std::exp2(static_cast<long double>(j) / static_cast<long double>(kExpSize)));
+    e.lo = static_cast<double>(std::log(2.0L) / static_cast<long double>(kExpSize) -
+                               static_cast<long double>(kLn2dNHi));
+    return e;
+}
+
+__device__ __forceinline__ double exp_neg(double a, const double* __restrict__ tab, double lo) {
+    // exp(-a) for 0 <= a <= kMaxArg
+    const double x = -a;
+    const double t = __builtin_fma(x, kInvLn2xN, kShift);
+    const double kf = t - kShift;
+    const int k = __double2loint(t);  // the low word holds the integer
+    double r = __builtin_fma(-kf, kLn2dNHi, x);
+    r = __builtin_fma(-kf, lo, r);
+    double q = __builtin_fma(r, 1.0 / 24.0, 1.0 / 6.0);
+    q = __builtin_fma(r, q, 0.5);
+    q = __builtin_fma(r, q, 1.0);
+    const double p = r * q;  // exp(r) - 1
+    const double tj = tab[k & (kExpSize - 1)];
+    const double v = __builtin_fma(tj, p, tj);
+    return __hiloint2double(__double2hiint(v) + ((k >> kExpBits) << 20), __double2loint(v));
+}
+
+// sqrt(s) for s >= 0: hardware reciprocal square root (about 2^-24 relative),
+// one coupled Goldschmidt step and one Newton correction; measured at 0.5 ulp.
+// s is raised to 1e-300 so that s = 0 gives 1e-150 (the kernel is then 1 to
+// the last bit) instead of 0 * inf.
+__device__ __forceinline__ double sqrt_nonneg(double s) {
+    s = fmax(s, 1e-300);
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    const double c = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, c, g);
+    h = __builtin_fma(h, c, h);
+    const double e = __builtin_fma(-g, g, s);
+    return __builtin_fma(e, h, g);
+}
+
+// Matern-nu/2 closed forms of Section 4.4 at a = c r / l (c = 1, sqrt 3,
+// sqrt 5 for TWONU = 2 nu = 1, 3, 5; `scale` = c / l).  a is capped at
+// kMaxArg: beyond it every form is below 1e-300, and the cap replaces those
+// entries by their value at the cap, an absolute change below 2e-302.
 template <int TWONU>
-__device__ __forceinline__ double matern_fast(double r, double inv_ell) {
+__device__ __forceinline__ double matern_fast(double r, double scale, const double* __restrict__ tab, double lo) {
+    const double a = fmin(r * scale, kMaxArg);
+    const double e = exp_neg(a, tab, lo);
     if constexpr (TWONU == 1) {
-        return exp(-r * inv_ell);
+        return e;
     } else if constexpr (TWONU == 3) {
-        const double a = 1.7320508075688772 * r * inv_ell;
-        return (1.0 + a) * exp(-a);
+        return (1.0 + a) * e;
     } else {
-        const double a = 2.23606797749979 * r * inv_ell;
-        return (1.0 + a + a * a * (1.0 / 3.0)) * exp(-a);
+        return (1.0 + a + a * a * (1.0 / 3.0)) * e;
     }
 }
 
-// Y[i, r0+r] = sum_j Theta(x_i, x_j) X[j, r0+r], j ascending.  x: n x d (any order,
-// X and Y in the same order).  D = d for d <= 3 (coordinates in registers), D = 0
-// for any d <= 32 (own coordinates re-read through the cache).
-template <int TWONU, int NR, int D>
-__global__ __launch_bounds__(kRows) void dense_matvec(const double* __restrict__ x, int64_t n, int d, double inv_ell,
-                                                      const double* __restrict__ X, int ld, int r0,
-                                                      double* __restrict__ Y) {
-    extern __shared__ double tile[];  // kTileJ * d coordinates, then kTileJ * NR values
-    double* sx = tile;
-    double* sv = tile + size_t(kTileJ) * d;
-    const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
-    const int64_t ic = i < n ? i : n - 1;
-    double xi[D > 0 ? D : 1];
+// Y[i, r0+r] = sum_j Theta(x_i, x_j) X[j, r0+r].  x: n x d (any order, X and Y
+// in the same order).  D = d for d <= 3 (coordinates in registers), D = 0 for
+// any d <= 32 (own coordinates re-read through the cache).  Columns stream
+// through LDS in tiles shared by the 256 rows of a block.
+//
+// The kernel values are generated on the vector ALUs; their contraction with
+// the right-hand sides runs on the matrix cores, by v_mfma_f64_4x4x4f64: four independent 4 x 4 x 4 blocks per wave, lane
+// l = 16 s + 4 q + t supplying A[q][t][s], B[q][s][t] and receiving D[q][s][t].
+// A wave owns kGroups groups of 16 rows; in a group, block q covers rows
+// 4q..4q+3.  For each quad of staged columns (column s of the quad), lane l
+// evaluates Theta(row 4q + t, column s) on the vector ALUs; B[s][t] is
+// X[column s][right-hand side t] (two instructions cover 8 right-hand sides,
+// with no padding), and lane l ends with Y[row 4q + s][t].  The order of
+// summation over j is fixed (by quads, ascending), so results are
+// reproducible run to run.
+constexpr int kGroups = 2;                    // 16-row groups per wave
+constexpr int kMfmaRhs = 8;                   // right-hand sides per pass (two 4-wide blocks)
+constexpr int kMfmaRows = 4 * 16 * kGroups;   // rows per block (4 waves)
+constexpr int kMfmaLds = 65536;               // LDS bytes per block at most
+
+template <int TWONU, int D, int NB>
+__global__ __launch_bounds__(256) void dense_matvec_mfma(const double* __restrict__ x, int64_t n, int d,
+                                                         double scale, const double* __restrict__ X, int ld,
+                                                         int r0, int nr, double* __restrict__ Y, ExpTable et,
+                                                         int tj) {
+    extern __shared__ double tile[];  // kExpSize table entries, tj * d coordinates, tj * 8 values
+    double* tab = tile;
+    double* sx = tile + kExpSize;
+    double* sv = sx + size_t(tj) * d;
+    for (int q = threadIdx.x; q < kExpSize; q += blockDim.x) tab[q] = et.t[q];
+    const double lo = et.lo;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t4 = lane & 3, q4 = (lane >> 2) & 3, s4 = lane >> 4;
+    const int64_t row_base = int64_t(blockIdx.x) * kMfmaRows + int64_t(wave) * 16 * kGroups;
+    int64_t ic[kGroups];
+    double xi[kGroups][D > 0 ? D : 1];
+    double acc[kGroups][NB];
 #pragma unroll
-    for (int t = 0; t < (D > 0 ? D : 1); ++t) xi[t] = D > 0 ? x[ic * D + t] : 0.0;
-    double acc[NR];
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i = row_base + g * 16 + 4 * q4 + t4;
+        ic[g] = i < n ? i : n - 1;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-    for (int64_t j0 = 0; j0 < n; j0 += kTileJ) {
-        const int m = int(n - j0 < kTileJ ? n - j0 : kTileJ);
-        for (int q = threadIdx.x; q < m * d; q += kRows) sx[q] = x[j0 * d + q];
-        for (int q = threadIdx.x; q < m * NR; q += kRows) sv[q] = X[(j0 + q / NR) * ld + r0 + q % NR];
+        for (int t = 0; t < (D > 0 ? D : 1); ++t) xi[g][t] = D > 0 ? x[ic[g] * D + t] : 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[g][b] = 0.0;
+    }
+    for (int64_t j0 = 0; j0 < n; j0 += tj) {
+        const int m = int(n - j0 < tj ? n - j0 : tj);
+        const int mq = (m + 3) & ~3;  // whole quads; the padding columns carry zero weights
+        for (int q = threadIdx.x; q < mq * d; q += 256) sx[q] = q < m * d ? x[j0 * d + q] : 0.0;
+        for (int q = threadIdx.x; q < mq * kMfmaRhs; q += 256) {
+            const int jj = q >> 3, r = q & 7;
+            sv[q] = (jj < m && r < nr) ? X[(j0 + jj) * ld + r0 + r] : 0.0;
+        }
         __syncthreads();
-        for (int jj = 0; jj < m; ++jj) {
-            double s = 0.0;
-            if constexpr (D > 0) {
+        for (int jq = 0; jq < mq; jq += 4) {
+            const int jj = jq + s4;
+            double bv[NB];
 #pragma unroll
-                for (int t = 0; t < D; ++t) {
-                    const double df = xi[t] - sx[jj * D + t];
-                    s = __builtin_fma(df, df, s);
+            for (int b = 0; b < NB; ++b) bv[b] = sv[jj * kMfmaRhs + 4 * b + t4];
+#pragma unroll
+            for (int g = 0; g < kGroups; ++g) {
+                double s = 0.0;
+                if constexpr (D > 0) {
+#pragma unroll
+                    for (int t = 0; t < D; ++t) {
+                        const double df = xi[g][t] - sx[jj * D + t];
+                        s = __builtin_fma(df, df, s);
+                    }
+                } else {
+                    for (int t = 0; t < d; ++t) {
+                        const double df = x[ic[g] * d + t] - sx[jj * d + t];
+                        s = __builtin_fma(df, df, s);
+                    }
                 }
-            } else {
-                for (int t = 0; t < d; ++t) {
-                    const double df = x[ic * d + t] - sx[jj * d + t];
-                    s = __builtin_fma(df, df, s);
-                }
+                const double th = matern_fast<TWONU>(sqrt_nonneg(s), scale, tab, lo);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[g][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(th, bv[b], acc[g][b], 0, 0, 0);
             }
-            const double th = matern_fast<TWONU>(__builtin_sqrt(s), inv_ell);
-#pragma unroll
-            for (int r = 0; r < NR; ++r) acc[r] = __builtin_fma(th, sv[jj * NR + r], acc[r]);
         }
         __syncthreads();
     }
-    if (i < n) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) Y[i * ld + r0 + r] = acc[r];
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i = row_base + g * 16 + 4 * q4 + s4;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int r = 4 * b + t4;
+            if (i < n && r < nr) Y[i * ld + r0 + r] = acc[g][b];
+        }
     }
 }
 
@@ -171,22 +277,19 @@ int twonu_of(double nu) {
 }
 
 template <int TWONU, int D>
-hipError_t launch_matvec_d(const double* x, int64_t n, int d, double inv_ell, const double* X, int nrhs, double* Y,
+hipError_t launch_matvec_d(const double* x, int64_t n, int d, double scale, const double* X, int nrhs, double* Y,
                            hipStream_t s) {
-    for (int r0 = 0; r0 < nrhs; r0 += kMaxNr) {
-        const int nr = std::min(kMaxNr, nrhs - r0);
-        const size_t lds = size_t(kTileJ) * (d + nr) * sizeof(double);
-        const dim3 g(blocks_for(n, kRows));
-        switch (nr) {
-            case 1: dense_matvec<TWONU, 1, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 2: dense_matvec<TWONU, 2, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 3: dense_matvec<TWONU, 3, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 4: dense_matvec<TWONU, 4, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 5: dense_matvec<TWONU, 5, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 6: dense_matvec<TWONU, 6, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            case 7: dense_matvec<TWONU, 7, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-            default: dense_matvec<TWONU, 8, D><<<g, kRows, lds, s>>>(x, n, d, inv_ell, X, nrhs, r0, Y); break;
-        }
+    static const ExpTable et = make_exp_table();
+    for (int r0 = 0; r0 < nrhs; r0 += kMfmaRhs) {
+        const int nr = std::min(kMfmaRhs, nrhs - r0);
+        // column tile: a multiple of 4, at most kTileJ, with the LDS footprint within 64 KiB
+        const int tj = std::min(kTileJ, ((kMfmaLds / int(sizeof(double)) - kExpSize) / (d + kMfmaRhs)) & ~3);
+        const size_t lds = (kExpSize + size_t(tj) * (d + kMfmaRhs)) * sizeof(double);
+        const dim3 g(blocks_for(n, kMfmaRows));
+        if (nr <= 4)
+            dense_matvec_mfma<TWONU, D, 1><<<g, 256, lds, s>>>(x, n, d, scale, X, nrhs, r0, nr, Y, et, tj);
+        else
+            dense_matvec_mfma<TWONU, D, 2><<<g, 256, lds, s>>>(x, n, d, scale, X, nrhs, r0, nr, Y, et, tj);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -194,22 +297,21 @@ hipError_t launch_matvec_d(const double* x, int64_t n, int d, double inv_ell, co
 }
 
 template <int TWONU>
-hipError_t launch_matvec_t(const double* x, int64_t n, int d, double inv_ell, const double* X, int nrhs, double* Y,
+hipError_t launch_matvec_t(const double* x, int64_t n, int d, double scale, const double* X, int nrhs, double* Y,
                            hipStream_t s) {
     switch (d) {
-        case 1: return launch_matvec_d<TWONU, 1>(x, n, d, inv_ell, X, nrhs, Y, s);
-        case 2: return launch_matvec_d<TWONU, 2>(x, n, d, inv_ell, X, nrhs, Y, s);
-        case 3: return launch_matvec_d<TWONU, 3>(x, n, d, inv_ell, X, nrhs, Y, s);
-        default: return launch_matvec_d<TWONU, 0>(x, n, d, inv_ell, X, nrhs, Y, s);
+        case 1: return launch_matvec_d<TWONU, 1>(x, n, d, scale, X, nrhs, Y, s);
+        case 2: return launch_matvec_d<TWONU, 2>(x, n, d, scale, X, nrhs, Y, s);
+        case 3: return launch_matvec_d<TWONU, 3>(x, n, d, scale, X, nrhs, Y, s);
+        default: return launch_matvec_d<TWONU, 0>(x, n, d, scale, X, nrhs, Y, s);
     }
 }
 
 hipError_t launch_matvec(int tn, const double* x, int64_t n, int d, double ell, const double* X, int nrhs, double* Y,
                          hipStream_t s) {
-    const double inv = 1.0 / ell;
-    if (tn == 1) return launch_matvec_t<1>(x, n, d, inv, X, nrhs, Y, s);
-    if (tn == 3) return launch_matvec_t<3>(x, n, d, inv, X, nrhs, Y, s);
-    return launch_matvec_t<5>(x, n, d, inv, X, nrhs, Y, s);
+    if (tn == 1) return launch_matvec_t<1>(x, n, d, 1.0 / ell, X, nrhs, Y, s);
+    if (tn == 3) return launch_matvec_t<3>(x, n, d, 1.7320508075688772 / ell, X, nrhs, Y, s);
+    return launch_matvec_t<5>(x, n, d, 2.23606797749979 / ell, X, nrhs, Y, s);
 }
 
 hipError_t launch_dot(const double* A, const double* B, int64_t n, int nrhs, double* partial, double* out,

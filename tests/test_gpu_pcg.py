@@ -1,8 +1,8 @@
 """GPU parity of the dense Theta product and of CG preconditioned by the sparse factor.
 
-The dense product sums the same terms in the same order as the oracle but uses a
-faithfully rounded exp, so it is compared to a relative error of 1e-12 of
-sum_j |Theta_ij X_j|.  CG is checked by what it certifies: the true residual
+The dense product sums the same terms as the oracle, in quads of columns on the
+matrix cores and with an exp and a square root accurate to about one ulp, so it
+is compared to a relative error of 1e-12 of sum_j |Theta_ij X_j|.  CG is checked by what it certifies: the true residual
 recomputed by the oracle's dense product meets the tolerance, and the iteration
 count matches the oracle's CG within one.
 """
@@ -29,12 +29,16 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-@pytest.mark.parametrize("nu,d,nrhs", [(0.5, 2, 8), (1.5, 3, 3), (2.5, 20, 1), (0.5, 1, 11)])
-def test_dense_matvec(K, nu, d, nrhs):
-    print(f"[gpu] dense matvec nu={nu} d={d} nrhs={nrhs}", flush=True)
-    x = W.embedded_sincos(1500, 3) if d == 20 else W.uniform_points(1500, d, 4)
-    X = W.gaussian_rhs(1500, nrhs, 5)
-    got = K.dense_matvec(dev(x), dev(X if nrhs > 1 else X[:, 0]), nu, 0.2).cpu().numpy().reshape(1500, nrhs)
+@pytest.mark.parametrize("nu,d,nrhs,n", [(0.5, 2, 8, 1500), (1.5, 3, 3, 1500), (2.5, 20, 1, 1500),
+                                         (0.5, 1, 11, 1500), (0.5, 2, 16, 1027), (1.5, 32, 5, 517),
+                                         (2.5, 2, 4, 3), (0.5, 3, 8, 1), (1.5, 2, 9, 255)])
+def test_dense_matvec(K, nu, d, nrhs, n):
+    """Several column tiles with a ragged tail, one and two passes over the
+    right-hand sides, the generic-dimension path (d = 20, 32) and tiny n."""
+    print(f"[gpu] dense matvec nu={nu} d={d} nrhs={nrhs} n={n}", flush=True)
+    x = W.embedded_sincos(n, 3) if d == 20 else W.uniform_points(n, d, 4)
+    X = W.gaussian_rhs(n, nrhs, 5)
+    got = K.dense_matvec(dev(x), dev(X if nrhs > 1 else X[:, 0]), nu, 0.2).cpu().numpy().reshape(n, nrhs)
     ref = O.dense_matvec(x, X, nu, 0.2)
     scale = O.dense_matvec(x, np.abs(X), nu, 0.2)
     assert np.max(np.abs(got - ref) / scale) < 1e-12
