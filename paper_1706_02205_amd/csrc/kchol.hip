@@ -98,43 +98,49 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 16 consecutive entries of a padded row, loaded as whole 64-byte (indices) and
-// 128-/64-byte (values) segments so every fetched sector is consumed at once.
-template <typename VT>
-struct RowWindow {
-    int idx[16];
-    VT val[16];
-    __device__ __forceinline__ void load(const int32_t* __restrict__ colidx, const VT* __restrict__ Lv, int64_t p) {
-        const int4* ip = reinterpret_cast<const int4*>(colidx + p);
+// Row windows.  L2 lines are 128 bytes, and with thousands of rows walked at
+// once a line is evicted before a lane comes back for its other half, so every
+// load below reads whole lines: 32 column indices (128 B) per window, and their
+// values as two 16-entry halves (128 B each, FP64) or at once (128 B, FP32).
+// Rows start on 32-entry boundaries, so windows are line-aligned.
+constexpr int kWin = 32;
+static_assert(kWin == kc::kRowAlign, "row windows must match the row alignment of the plan");
+
+__device__ __forceinline__ void load_idx32(const int32_t* __restrict__ colidx, int64_t p, int (&idx)[kWin]) {
+    const int4* ip = reinterpret_cast<const int4*>(colidx + p);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int4 v = ip[q];
-            idx[4 * q] = v.x;
-            idx[4 * q + 1] = v.y;
-            idx[4 * q + 2] = v.z;
-            idx[4 * q + 3] = v.w;
-        }
-        if constexpr (sizeof(VT) == 8) {
-            const double2* vp = reinterpret_cast<const double2*>(Lv + p);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                double2 v = vp[q];
-                val[2 * q] = v.x;
-                val[2 * q + 1] = v.y;
-            }
-        } else {
-            const float4* vp = reinterpret_cast<const float4*>(Lv + p);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                float4 v = vp[q];
-                val[4 * q] = v.x;
-                val[4 * q + 1] = v.y;
-                val[4 * q + 2] = v.z;
-                val[4 * q + 3] = v.w;
-            }
-        }
+    for (int q = 0; q < kWin / 4; ++q) {
+        const int4 v = ip[q];
+        idx[4 * q] = v.x;
+        idx[4 * q + 1] = v.y;
+        idx[4 * q + 2] = v.z;
+        idx[4 * q + 3] = v.w;
     }
-};
+}
+
+template <int N>
+__device__ __forceinline__ void load_vals(const double* __restrict__ Lv, int64_t p, double (&val)[N]) {
+    const double2* vp = reinterpret_cast<const double2*>(Lv + p);
+#pragma unroll
+    for (int q = 0; q < N / 2; ++q) {
+        const double2 v = vp[q];
+        val[2 * q] = v.x;
+        val[2 * q + 1] = v.y;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void load_vals(const float* __restrict__ Lv, int64_t p, float (&val)[N]) {
+    const float4* vp = reinterpret_cast<const float4*>(Lv + p);
+#pragma unroll
+    for (int q = 0; q < N / 4; ++q) {
+        const float4 v = vp[q];
+        val[4 * q] = v.x;
+        val[4 * q + 1] = v.y;
+        val[4 * q + 2] = v.z;
+        val[4 * q + 3] = v.w;
+    }
+}
 
 // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
 // Renumber them so that each XCD receives one contiguous range of blocks: the
@@ -160,7 +166,7 @@ __device__ __forceinline__ int xcd_block() {
 //
 // A wavefront owns 64 consecutive entries of one column (a Unit), one entry k
 // per lane.  Row j's parents (indices and L_ji) are staged once in LDS.  Each
-// lane then streams row k of L -- stored by rows, padded to 16-entry windows --
+// lane then streams row k of L -- stored by rows, padded to 32-entry windows --
 // from its start up to the entry (k,j), whose position is known from the
 // CSC->CSR map, and merges it against the staged row j with a cursor.  The pivot
 // A_jj is accumulated by every wave of column j from the staged row j, so the
@@ -222,20 +228,37 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(
     if (active) {
         const int64_t pend = csc2csr[e];  // position of (k,j) in row k
         int q = 0;
-        for (int64_t p = rowptr[k]; p < pend; p += 16) {
-            RowWindow<VT> w;
-            w.load(colidx, Lv, p);
+        // values of one load: FP64 in 16-entry halves, FP32 a whole window (one line each).
+        // Loading all 32 FP64 values at once costs registers, hence occupancy, and
+        // measured slower; so did 8-entry pieces (more round trips).
+        constexpr int kHalf = sizeof(VT) == 8 ? 16 : kWin;
+        auto merge = [&](const int (&idx)[kWin], const VT (&val)[kHalf], int off, int lim) {
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                if (p + t < pend) {
-                    const int i = w.idx[t];
+            for (int t = 0; t < kHalf; ++t) {
+                if (off + t < lim) {
+                    const int i = idx[off + t];
                     while (sidx[q] < i) ++q;
                     if (sidx[q] == i) {
                         const VT lji = sval[q];
-                        if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-w.val[t], lji, acc);
-                        else acc = __builtin_fmaf(-w.val[t], lji, acc);
+                        if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-val[t], lji, acc);
+                        else acc = __builtin_fmaf(-val[t], lji, acc);
                         if (COUNT && lji != VT(0)) ++hits;
                     }
+                }
+            }
+        };
+        for (int64_t p = rowptr[k]; p < pend; p += kWin) {
+            const int lim = pend - p < kWin ? int(pend - p) : kWin;  // entries of this window before (k,j)
+            int idx[kWin];
+            load_idx32(colidx, p, idx);
+            VT val[kHalf];
+            load_vals(Lv, p, val);
+            merge(idx, val, 0, lim);
+#pragma unroll
+            for (int off = kHalf; off < kWin; off += kHalf) {
+                if (off < lim) {
+                    load_vals(Lv, p + off, val);
+                    merge(idx, val, off, lim);
                 }
             }
         }

@@ -15,7 +15,7 @@ struct Unit {
     int32_t first;  // offset of the chunk's first entry inside column j
 };
 
-constexpr int kRowAlign = 16;
+constexpr int kRowAlign = 32;
 
 // Backward solve of a long column: one piece of its dot product ...
 struct BwdChunk {
