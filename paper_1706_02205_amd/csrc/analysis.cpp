@@ -4,8 +4,9 @@
 // max-rule, or the min-rule of Section 6.2).  Like the paper's SortSparse
 // algorithm (Section 4.1) the ordering is produced with a mutable max-heap of
 // current distances, but the candidate points to update are found with a k-d
-// tree range search of radius l[i] around the newly selected point instead of
-// parent/child lists.  Every comparison that decides the output uses the same
+// tree search around the newly selected point instead of parent/child lists:
+// a subtree is entered only if its box may hold an unselected point closer than
+// that point's current distance (per-node upper bounds of those distances).  Every comparison that decides the output uses the same
 // floating-point expression as the definition, so the result is exactly the
 // greedy maximin ordering and exactly S_rho:
 //   dist(a,b) = sqrt(sum_t (a_t - b_t)^2), summed over t ascending, no fma;
@@ -171,49 +172,89 @@ struct KDTree {
             }
         }
     }
+
+    // Ordering update around q.  ub[node] bounds m[j] from above for every
+    // unselected point j of the node (m only decreases, so a stale bound stays
+    // valid).  A node is entered only if its box may hold a point closer to q
+    // than that bound -- the only points whose m can change.  leaf(begin, end)
+    // updates a leaf and returns the exact maximum of m over its unselected
+    // points (-inf if none), which becomes the leaf's bound; inner nodes take
+    // the maximum of their children.
+    template <class F>
+    double relax(int32_t id, const double* q, std::vector<double>& ub, F& leaf) const {
+        if (!(boxdist(id, q) < ub[size_t(id)])) return ub[size_t(id)];
+        const Node& nd = nodes[size_t(id)];
+        const double u = nd.left < 0 ? leaf(nd.begin, nd.end)
+                                     : std::max(relax(nd.left, q, ub, leaf), relax(nd.right, q, ub, leaf));
+        ub[size_t(id)] = u;
+        return u;
+    }
 };
 
-// Indexed binary max-heap on (m[j] descending, j ascending).
+// Indexed 4-ary max-heap on (key descending, id ascending), keys stored inline:
+// a level of a sift reads one 64-byte group of children instead of chasing ids
+// into the key array (a cache miss per comparison on large inputs).  The order
+// is strict and total, so the sequence of pops is that of any correct heap.
 struct MaxHeap {
-    std::vector<int32_t> heap, pos;
-    const std::vector<double>* m;
+    struct Entry {
+        double key;
+        int32_t id;   // original index: breaks ties
+        int32_t slot; // caller's slot of the entry (pos is indexed by it)
+    };
+    std::vector<Entry> store;
+    Entry* h = nullptr;  // h[0] is the root; children of i are 4i+1 .. 4i+4
+    std::vector<int32_t> pos;
     int64_t size = 0;
 
-    bool greater(int32_t a, int32_t b) const {
-        double ma = (*m)[a], mb = (*m)[b];
-        return ma > mb || (ma == mb && a < b);
-    }
-    void init(int64_t n, const std::vector<double>* key) {
-        m = key;
-        heap.resize(n);
-        pos.resize(n);
-        for (int64_t i = 0; i < n; ++i) heap[i] = pos[i] = int32_t(i);
+    static bool greater(const Entry& a, const Entry& b) { return a.key > b.key || (a.key == b.key && a.id < b.id); }
+    // entry s has key[s], original index id[s] and slot s
+    void init(int64_t n, const double* key, const int32_t* id) {
+        // element 1 on a 64-byte boundary, so every group of 4 children shares one line
+        store.resize(size_t(n) + 8);
+        const uintptr_t base = reinterpret_cast<uintptr_t>(store.data());
+        const uintptr_t want = ((base + 16 + 63) & ~uintptr_t(63)) - 16;
+        h = reinterpret_cast<Entry*>(want);
+        pos.resize(size_t(n));
+        for (int64_t i = 0; i < n; ++i) {
+            h[i] = Entry{key[i], id[i], int32_t(i)};
+            pos[size_t(i)] = int32_t(i);
+        }
         size = n;
-        for (int64_t i = n / 2 - 1; i >= 0; --i) sift_down(i);
+        for (int64_t i = (n - 2) / 4; i >= 0; --i) sift_down(i);
     }
     void sift_down(int64_t i) {
-        int32_t v = heap[i];
+        const Entry v = h[i];
         for (;;) {
-            int64_t c = 2 * i + 1;
+            const int64_t c = 4 * i + 1;
             if (c >= size) break;
-            if (c + 1 < size && greater(heap[c + 1], heap[c])) ++c;
-            if (!greater(heap[c], v)) break;
-            heap[i] = heap[c];
-            pos[heap[i]] = int32_t(i);
-            i = c;
+            const int64_t ce = std::min<int64_t>(c + 4, size);
+            int64_t best = c;
+            for (int64_t k = c + 1; k < ce; ++k)
+                if (greater(h[k], h[best])) best = k;
+            if (!greater(h[best], v)) break;
+            h[i] = h[best];
+            pos[size_t(h[i].slot)] = int32_t(i);
+            i = best;
         }
-        heap[i] = v;
-        pos[v] = int32_t(i);
+        h[i] = v;
+        pos[size_t(v.slot)] = int32_t(i);
     }
+    // the key of slot s decreased to `key`
+    void decrease(int32_t s, double key) {
+        const int64_t i = pos[size_t(s)];
+        h[i].key = key;
+        sift_down(i);
+    }
+    // removes the maximum; returns its slot
     int32_t pop() {
-        int32_t top = heap[0];
+        const int32_t top = h[0].slot;
         --size;
         if (size > 0) {
-            heap[0] = heap[size];
-            pos[heap[0]] = 0;
+            h[0] = h[size];
+            pos[size_t(h[0].slot)] = 0;
             sift_down(0);
         }
-        pos[top] = -1;
+        pos[size_t(top)] = -1;
         return top;
     }
 };
@@ -224,28 +265,38 @@ void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t*
     (void)nthreads;
     KDTree tree;
     tree.build(x, n, d);
+    // The working arrays are laid out in tree order (slot t holds point tree.idx[t]),
+    // so that scanning a leaf reads contiguous memory.
+    std::vector<double> xt(size_t(n) * d);
+    for (int64_t t = 0; t < n; ++t)
+        std::copy(x + size_t(tree.idx[t]) * d, x + size_t(tree.idx[t] + 1) * d, xt.begin() + size_t(t) * d);
     std::vector<double> m(static_cast<size_t>(n), std::numeric_limits<double>::infinity());
     std::vector<char> sel(static_cast<size_t>(n), 0);
     MaxHeap heap;
-    heap.init(n, &m);
-    for (int64_t k = 0; k < n; ++k) {
-        int32_t i = heap.pop();
-        perm[k] = i;
-        l[k] = m[i];
-        sel[i] = 1;
-        const double* xi = x + size_t(i) * d;
-        // Only points with dist(x_j, x_i) < m[j] <= m[i] change.
-        tree.visit(xi, m[i], 0, int32_t(n - 1), [&](int32_t b, int32_t e) {
-            for (int32_t t = b; t < e; ++t) {
-                int32_t j = tree.idx[t];
-                if (sel[j]) continue;
-                double dj = dist(x + size_t(j) * d, xi, d);
-                if (dj < m[j]) {
-                    m[j] = dj;
-                    heap.sift_down(heap.pos[j]);
-                }
+    heap.init(n, m.data(), tree.idx.data());
+    std::vector<double> ub(tree.nodes.size(), std::numeric_limits<double>::infinity());
+    const double* xi = nullptr;
+    auto leaf_update = [&](int32_t b, int32_t e) {
+        double u = -std::numeric_limits<double>::infinity();
+        for (int32_t t = b; t < e; ++t) {
+            if (sel[size_t(t)]) continue;
+            const double dj = dist(xt.data() + size_t(t) * d, xi, d);
+            if (dj < m[size_t(t)]) {
+                m[size_t(t)] = dj;
+                heap.decrease(t, dj);
             }
-        });
+            u = std::max(u, m[size_t(t)]);
+        }
+        return u;
+    };
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t t = heap.pop();
+        perm[k] = tree.idx[size_t(t)];
+        l[k] = m[size_t(t)];
+        sel[size_t(t)] = 1;
+        xi = xt.data() + size_t(t) * d;
+        // Only points with dist(x_j, x_i) < m[j] change.
+        tree.relax(0, xi, ub, leaf_update);
     }
 }
 
@@ -377,6 +428,13 @@ void build_pattern(Plan& p, int nthreads) {
     KDTree tree;
     tree.build(xh, n, d);
     p.spatial = tree.idx;  // k-d tree leaf order: positions grouped by region
+    // points copied into tree order, so that scanning a leaf reads contiguous memory
+    const std::vector<int32_t>& idt = tree.idx;
+    std::vector<double> xt(size_t(n) * d);
+    parallel_for(nthreads, n, 1 << 14, [&](int64_t t0, int64_t t1, int) {
+        for (int64_t t = t0; t < t1; ++t)
+            std::copy(xh + size_t(idt[size_t(t)]) * d, xh + size_t(idt[size_t(t)] + 1) * d, xt.begin() + size_t(t) * d);
+    });
 
     if (p.rule == KC_RULE_MAX) {
         // column b: the diagonal, then rows a > b with dist(x_a, x_b) <= rho * max(l_a, l_b) = rho * l_b
@@ -387,8 +445,8 @@ void build_pattern(Plan& p, int nthreads) {
             const size_t first = out.size();
             tree.visit(xb, R, int32_t(b + 1), int32_t(n - 1), [&](int32_t s, int32_t e) {
                 for (int32_t t = s; t < e; ++t) {
-                    const int32_t a = tree.idx[t];
-                    if (a > b && within(xh + size_t(a) * d, xb, d, R, R2)) out.push_back(a);
+                    const int32_t a = idt[size_t(t)];
+                    if (a > b && within(xt.data() + size_t(t) * d, xb, d, R, R2)) out.push_back(a);
                 }
             });
             std::sort(out.begin() + first, out.end());
@@ -402,8 +460,8 @@ void build_pattern(Plan& p, int nthreads) {
             const double R = p.rho * p.l[size_t(a)], R2 = r2_bound(R);
             tree.visit(xa, R, 0, int32_t(a - 1), [&](int32_t s, int32_t e) {
                 for (int32_t t = s; t < e; ++t) {
-                    const int32_t b = tree.idx[t];
-                    if (b < a && within(xa, xh + size_t(b) * d, d, R, R2)) out.push_back(b);
+                    const int32_t b = idt[size_t(t)];
+                    if (b < a && within(xa, xt.data() + size_t(t) * d, d, R, R2)) out.push_back(b);
                 }
             });
         }, rp, cols);
@@ -682,7 +740,7 @@ void supernodal_transform(Plan& p, int nthreads) {
         for (int64_t q = sptr[size_t(s)]; q < sptr[size_t(s + 1)]; ++q) colptr[size_t(q + 1)] = below + (sptr[size_t(s + 1)] - q);
     }
     for (int64_t q = 0; q < n; ++q) colptr[size_t(q + 1)] += colptr[size_t(q)];
-    std::vector<int32_t> rowidx(size_t(colptr[size_t(n)]));
+    std::vector<int32_t> rowidx(static_cast<size_t>(colptr[static_cast<size_t>(n)]));
     parallel_for(nthreads, ns, 64, [&](int64_t s0, int64_t s1, int) {
         for (int64_t s = s0; s < s1; ++s)
             for (int64_t q = sptr[size_t(s)]; q < sptr[size_t(s + 1)]; ++q) {
