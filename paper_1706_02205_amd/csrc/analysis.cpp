@@ -538,7 +538,12 @@ void build_schedule(Plan& p, int nthreads) {
     for (int32_t v = 0; v < nrl; ++v) p.bwd_off[v + 1] += p.bwd_off[v];
     p.bwd_cols.resize(size_t(n));
     std::vector<int64_t> bf(p.bwd_off.begin(), p.bwd_off.end() - 1);
-    for (int64_t j = n - 1; j >= 0; --j) p.bwd_cols[size_t(bf[rl[j]]++)] = int32_t(j);
+    // within a level, columns follow the k-d tree leaf order (as the forward
+    // rows do), so that neighbouring work touches the same solution rows
+    for (int64_t t = 0; t < n; ++t) {
+        const int32_t j = p.spatial[size_t(t)];
+        p.bwd_cols[size_t(bf[rl[j]]++)] = j;
+    }
 }
 
 }  // namespace kc

@@ -38,7 +38,8 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 wavefronts
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int64_t kLongColumn = 2048;          // backward solve: longer columns are reduced in pieces
-constexpr int64_t kChunk = 2048;               // entries per partial dot product of a long column
+constexpr int64_t kChunk = 512;                // entries per partial dot product of a long column
+constexpr int kAhead = 4;                      // solve sweeps: 64-entry chunks fetched at once
 constexpr int kMaxRhsPerPass = 8;
 
 enum Counter { kNonpos = 0, kShifted = 1, kUpdates = 2, kExpHard = 3, kNumCounters = 8 };
@@ -315,6 +316,27 @@ __device__ __forceinline__ double diag_value(const VT* Lv, const double* diag, i
     else return diag[k];
 }
 
+// acc -= sum_q sL[q] * sY[q * NR + lane] for q = 0..m-1 in ascending order (the
+// sequential substitution).  LDS reads are issued eight at a time so that their
+// latency is paid once per eight dependent fmas.
+template <int NR>
+__device__ __forceinline__ double apply_chunk(const double* __restrict__ sL, const double* __restrict__ sY, int m,
+                                              int lane, double acc) {
+    int q = 0;
+    for (; q + 8 <= m; q += 8) {
+        double a[8], v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = sL[q + u];
+            v[u] = sY[(q + u) * NR + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = __builtin_fma(-a[u], v[u], acc);
+    }
+    for (; q < m; ++q) acc = __builtin_fma(-sL[q], sY[q * NR + lane], acc);
+    return acc;
+}
+
 template <typename VT, int NR>
 __global__ __launch_bounds__(kBlock) void fwd_solve(const int32_t* __restrict__ rows, int64_t beg, int64_t end,
                                                     const int64_t* __restrict__ rowptr,
@@ -327,26 +349,44 @@ __global__ __launch_bounds__(kBlock) void fwd_solve(const int32_t* __restrict__ 
     __shared__ double sY[kWavesPerBlock][kWave * NR];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
     if (t >= end) return;
     const int k = __builtin_amdgcn_readfirstlane(rows[t]);
     const int64_t p0 = rowptr[k], pd = rowend[k] - 1;  // pd: the diagonal
     double acc = 0.0;
     if (lane < NR) acc = b[int64_t(perm[k]) * ld + r0 + lane];
-    for (int64_t c = p0; c < pd; c += kWave) {
-        const int64_t p = c + lane;
-        if (p < pd) {
-            sL[wave][lane] = double(Lv[p]);
-            const double* yi = y + int64_t(colidx[p]) * ld + r0;
+    // kAhead chunks of the row are fetched at once -- their indices and L values,
+    // then the gathered right-hand-side rows (parents' values are final: earlier
+    // levels) -- so a row costs two memory latencies per kAhead * 64 entries
+    for (int64_t cb = p0; cb < pd; cb += kAhead * kWave) {
+        int ci[kAhead];
+        double lv[kAhead], yv[kAhead][NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = yi[r];
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t p = cb + int64_t(u) * kWave + lane;
+            ci[u] = p < pd ? colidx[p] : -1;
+            lv[u] = p < pd ? double(Lv[p]) : 0.0;
         }
-        wave_lds_sync();
-        if (lane < NR) {
-            const int m = int(pd - c < kWave ? pd - c : kWave);
-            for (int q = 0; q < m; ++q) acc = __builtin_fma(-sL[wave][q], sY[wave][q * NR + lane], acc);
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (ci[u] >= 0) {
+                const double* yi = y + int64_t(ci[u]) * ld + r0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) yv[u][r] = yi[r];
+            }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t c = cb + int64_t(u) * kWave;
+            if (c >= pd) break;
+            if (ci[u] >= 0) {
+                sL[wave][lane] = lv[u];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = yv[u][r];
+            }
+            wave_lds_sync();
+            if (lane < NR) acc = apply_chunk<NR>(sL[wave], sY[wave], int(pd - c < kWave ? pd - c : kWave), lane, acc);
+            wave_lds_sync();
         }
-        wave_lds_sync();
     }
     if (lane < NR) {
         const double lkk = diag_value(Lv, diag, pd, k);
@@ -365,26 +405,43 @@ __global__ __launch_bounds__(kBlock) void bwd_solve(const int32_t* __restrict__ 
     __shared__ double sY[kWavesPerBlock][kWave * NR];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
     if (t >= end) return;
     const int j = __builtin_amdgcn_readfirstlane(cols[t]);
     const int64_t c0 = colptr[j], c1 = colptr[j + 1];
     double acc = 0.0;
     if (lane < NR) acc = y[int64_t(j) * ld + r0 + lane];
-    for (int64_t c = c0 + 1; c < c1; c += kWave) {
-        const int64_t e = c + lane;
-        if (e < c1) {
-            sL[wave][lane] = double(Lcsc[e]);
-            const double* xk = y + int64_t(rowidx[e]) * ld + r0;
+    // kAhead chunks fetched at once, as in the forward sweep (rows below j are
+    // final: earlier reverse levels)
+    for (int64_t cb = c0 + 1; cb < c1; cb += kAhead * kWave) {
+        int ri[kAhead];
+        double lv[kAhead], yv[kAhead][NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = xk[r];
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t e = cb + int64_t(u) * kWave + lane;
+            ri[u] = e < c1 ? rowidx[e] : -1;
+            lv[u] = e < c1 ? double(Lcsc[e]) : 0.0;
         }
-        wave_lds_sync();
-        if (lane < NR) {
-            const int m = int(c1 - c < kWave ? c1 - c : kWave);
-            for (int q = 0; q < m; ++q) acc = __builtin_fma(-sL[wave][q], sY[wave][q * NR + lane], acc);
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (ri[u] >= 0) {
+                const double* xk = y + int64_t(ri[u]) * ld + r0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) yv[u][r] = xk[r];
+            }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t c = cb + int64_t(u) * kWave;
+            if (c >= c1) break;
+            if (ri[u] >= 0) {
+                sL[wave][lane] = lv[u];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = yv[u][r];
+            }
+            wave_lds_sync();
+            if (lane < NR) acc = apply_chunk<NR>(sL[wave], sY[wave], int(c1 - c < kWave ? c1 - c : kWave), lane, acc);
+            wave_lds_sync();
         }
-        wave_lds_sync();
     }
     if (lane < NR) {
         const double ljj = diag_value(Lcsc, diag, c0, j);
@@ -403,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
                                                       const double* __restrict__ y, double* __restrict__ partial) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
     if (t >= end) return;
     const kc::BwdChunk ch = chunks[t];
     const int64_t e0 = colptr[ch.col] + 1 + ch.start;
@@ -411,11 +468,27 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] = 0.0;
-    for (int64_t e = e0 + lane; e < e1; e += kWave) {
-        const double l = double(Lcsc[e]);
-        const double* xk = y + int64_t(rowidx[e]) * ld + r0;
+    // four entries per lane in flight at once, applied in ascending order
+    constexpr int kDepth = 4;
+    for (int64_t e = e0 + lane; e < e1; e += kDepth * kWave) {
+        double l[kDepth], v[kDepth][NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) s[r] = __builtin_fma(l, xk[r], s[r]);
+        for (int u = 0; u < kDepth; ++u) {
+            const int64_t eu = e + int64_t(u) * kWave;
+            l[u] = 0.0;
+            if (eu < e1) {
+                l[u] = double(Lcsc[eu]);
+                const double* xk = y + int64_t(rowidx[eu]) * ld + r0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) v[u][r] = xk[r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u)
+            if (e + int64_t(u) * kWave < e1) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) s[r] = __builtin_fma(l[u], v[u][r], s[r]);
+            }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
@@ -441,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void bwd_combine(const kc::LongCol* __restr
                                                       double* __restrict__ x) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int64_t t = beg + int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
     if (t >= end) return;
     const kc::LongCol lc = lcols[t];
     double s[NR];
