@@ -73,12 +73,15 @@ class ServeStats:
 
 class Server:
     def __init__(self, nu: float, lengthscale: float, rho: float, prec: str = "mixed", budget_bytes: float = 64e9,
-                 max_inflight: int = 8, nstreams: int = 4, analysis_threads: int = 8, analysis_nthreads: int = 4):
+                 max_inflight: int = 8, nstreams: int = 4, analysis_threads: int = 8,
+                 analysis_nthreads: Optional[int] = None):
         import torch
         self.nu, self.ell, self.rho, self.prec = nu, lengthscale, rho, prec
         self.pivot, self.tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
         self.budget = int(budget_bytes)
-        self.analysis_nthreads = analysis_nthreads  # host threads inside one request's analysis
+        # host threads inside one request's analysis; None: by size, one per 25,000 points (1 to 8), so
+        # that the largest requests -- the latency tail -- get the most threads
+        self.analysis_nthreads = analysis_nthreads
         self.max_inflight = max_inflight
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.pool = ThreadPoolExecutor(max_workers=analysis_threads)
@@ -97,8 +100,10 @@ class Server:
         res = RequestResult(rid, len(points), 0, arrival if arrival is not None else time.perf_counter())
         self.results[rid] = res
 
+        nth = self.analysis_nthreads or max(1, min(8, len(points) // 25_000))
+
         def work():
-            plan = analyze(points, self.rho, nthreads=self.analysis_nthreads)
+            plan = analyze(points, self.rho, nthreads=nth)
             res.analyzed = time.perf_counter()
             res.nnz = plan.nnz
             with self._lock:
