@@ -136,6 +136,15 @@ kc_status kc_plan_info(const kc_plan *plan, kc_plan_info_t *info);
 kc_status kc_plan_export(const kc_plan *plan, int32_t *perm, double *l, int64_t *colptr, int32_t *rowidx);
 /* Level of each column in the elimination DAG (column j waits for every i<j with (j,i) in S). */
 kc_status kc_plan_levels(const kc_plan *plan, int32_t *level);
+/* The factorization reads the column indices of each row of S as 16-bit gaps
+ * between consecutive indices; a gap of at least `delta_limit` is kept as a
+ * full index in a per-row escape list.  The default, 65536, is the largest
+ * gap 16 bits hold.  A smaller limit (1 <= delta_limit <= 65536) re-encodes
+ * the plan with more escapes -- every entry for 1 -- and yields the same
+ * factor; it exists to exercise the escape path.  Factors created afterwards
+ * use the new encoding.  Returns the number of escapes in *nescapes (may be NULL).
+ * KC_EINVAL for a limit out of range. */
+kc_status kc_plan_set_delta_limit(kc_plan *plan, uint32_t delta_limit, int64_t *nescapes);
 void kc_plan_destroy(kc_plan *plan);
 
 /* ---------------------------------------------------------------- factor */

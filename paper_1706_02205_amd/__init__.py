@@ -83,6 +83,14 @@ class Plan:
         _lib.check(_lib.load().kc_plan_levels(self._h, _ptr(lv)), "kc_plan_levels")
         return lv
 
+    def set_delta_limit(self, limit: int) -> int:
+        """Re-encode the 16-bit row-index gaps with escapes for gaps >= limit (1..65536; default 65536).
+        The factor is the same for every limit; small limits exercise the escape path.  Returns the
+        number of escapes."""
+        ne = C.c_int64()
+        _lib.check(_lib.load().kc_plan_set_delta_limit(self._h, int(limit), C.byref(ne)), "kc_plan_set_delta_limit")
+        return int(ne.value)
+
 
 def analyze(x: np.ndarray, rho: float, rule: str = "max", nthreads: int = 0) -> Plan:
     """Maximin ordering + pattern S_rho + level schedule (Section 2.3) on the host."""

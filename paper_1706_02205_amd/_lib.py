@@ -35,7 +35,7 @@ class kc_factor_stats_t(C.Structure):
                 ("updates", C.c_int64), ("exp_hard", C.c_int64)]
 
 
-EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "kc_plan_export", "kc_plan_levels",
+EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "kc_plan_export", "kc_plan_levels", "kc_plan_set_delta_limit",
             "kc_plan_destroy", "kc_factor_bytes", "kc_factor_create", "kc_factorize", "kc_theta", "kc_solve_bytes",
             "kc_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
             "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
@@ -70,6 +70,7 @@ def load():
         "kc_plan_info": (C.c_int, [vp, P(kc_plan_info_t)]),
         "kc_plan_export": (C.c_int, [vp, vp, vp, vp, vp]),
         "kc_plan_levels": (C.c_int, [vp, vp]),
+        "kc_plan_set_delta_limit": (C.c_int, [vp, C.c_uint32, vp]),
         "kc_plan_destroy": (None, [vp]),
         "kc_factor_bytes": (C.c_int, [vp, C.c_int, P(sz)]),
         "kc_factor_create": (C.c_int, [vp, C.c_int, vp, sz, vp, P(vp)]),

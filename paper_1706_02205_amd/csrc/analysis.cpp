@@ -355,6 +355,7 @@ void csr_from_csc(Plan& p, int nthreads) {
                 }
         }
     });
+    encode_row_deltas(p, nthreads);
 }
 
 }  // namespace
@@ -419,6 +420,40 @@ void collect(int nthreads, int64_t n, Scan&& scan, std::vector<int64_t>& ptr, st
 }
 
 }  // namespace
+
+void encode_row_deltas(Plan& p, int nthreads) {
+    nthreads = resolve_threads(nthreads);
+    const int64_t n = p.n;
+    const int64_t lim = p.delta_limit;
+    p.cdelta.assign(size_t(p.nnz_rows()), 0);
+    std::vector<uint32_t> cnt(static_cast<size_t>(n), 0);
+    parallel_for(nthreads, n, 1 << 12, [&](int64_t k0, int64_t k1, int) {
+        for (int64_t k = k0; k < k1; ++k) {
+            int64_t prev = -1;
+            uint32_t c = 0;
+            for (int64_t q = p.rowptr[k]; q < p.rowend[k]; ++q) {
+                const int64_t g = int64_t(p.colidx[size_t(q)]) - prev;
+                if (g >= lim) ++c;
+                else p.cdelta[size_t(q)] = uint16_t(g);
+                prev = p.colidx[size_t(q)];
+            }
+            cnt[size_t(k)] = c;
+        }
+    });
+    p.escptr.assign(size_t(n + 1), 0);
+    for (int64_t k = 0; k < n; ++k) p.escptr[size_t(k + 1)] = p.escptr[size_t(k)] + cnt[size_t(k)];
+    p.esc.assign(size_t(p.escptr[size_t(n)]), 0);
+    parallel_for(nthreads, n, 1 << 12, [&](int64_t k0, int64_t k1, int) {
+        for (int64_t k = k0; k < k1; ++k) {
+            int64_t prev = -1;
+            uint32_t w = p.escptr[size_t(k)];
+            for (int64_t q = p.rowptr[k]; q < p.rowend[k]; ++q) {
+                if (int64_t(p.colidx[size_t(q)]) - prev >= lim) p.esc[size_t(w++)] = p.colidx[size_t(q)];
+                prev = p.colidx[size_t(q)];
+            }
+        }
+    });
+}
 
 void build_pattern(Plan& p, int nthreads) {
     nthreads = resolve_threads(nthreads);
@@ -611,6 +646,7 @@ void merge_plans(const std::vector<Plan>& parts, Plan& out) {
         e0 += p.nnz();
         q0 += p.nnz_rows();
     }
+    encode_row_deltas(out, 0);
     // level-major merge of units and forward rows
     out.unit_off.assign(size_t(out.nlevels + 1), 0);
     out.fwd_off.assign(size_t(out.nlevels + 1), 0);

@@ -25,6 +25,9 @@ struct kc_factor {
     int64_t* rowptr = nullptr;
     int64_t* rowend = nullptr;
     int32_t* colidx = nullptr;
+    uint32_t* cdelta = nullptr;  // 16-bit row-index gaps, two per word
+    uint32_t* escptr = nullptr;
+    int32_t* esc = nullptr;
     void* L = nullptr;        // by rows: double[nnz_rows] or float[nnz_rows]
     void* Lcsc = nullptr;     // by columns: double[nnz] or float[nnz]
     double* diag = nullptr;   // MIXED only

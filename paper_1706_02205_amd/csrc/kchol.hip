@@ -101,21 +101,23 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Row windows.  L2 lines are 128 bytes, and with thousands of rows walked at
 // once a line is evicted before a lane comes back for its other half, so every
-// load below reads whole lines: 32 column indices (128 B) per window, and their
-// values as two 16-entry halves (128 B each, FP64) or at once (128 B, FP32).
-// Rows start on 32-entry boundaries, so windows are line-aligned.
-constexpr int kWin = 32;
+// load below reads whole lines: 64 column-index gaps (16 bits each, 128 B) per
+// window, and their values in 16-entry pieces (128 B each, FP64) or 32-entry
+// pieces (128 B, FP32).  Rows start on 64-entry boundaries, so windows are
+// line-aligned.
+constexpr int kWin = 64;
+constexpr int kEscQ = 2;  // escapes of a row held in registers; later ones are read when met
 static_assert(kWin == kc::kRowAlign, "row windows must match the row alignment of the plan");
 
-__device__ __forceinline__ void load_idx32(const int32_t* __restrict__ colidx, int64_t p, int (&idx)[kWin]) {
-    const int4* ip = reinterpret_cast<const int4*>(colidx + p);
+__device__ __forceinline__ void load_gaps(const uint32_t* __restrict__ cdelta, int64_t p, uint32_t (&w)[kWin / 2]) {
+    const uint4* ip = reinterpret_cast<const uint4*>(cdelta + p / 2);
 #pragma unroll
-    for (int q = 0; q < kWin / 4; ++q) {
-        const int4 v = ip[q];
-        idx[4 * q] = v.x;
-        idx[4 * q + 1] = v.y;
-        idx[4 * q + 2] = v.z;
-        idx[4 * q + 3] = v.w;
+    for (int q = 0; q < kWin / 8; ++q) {
+        const uint4 v = ip[q];
+        w[4 * q] = v.x;
+        w[4 * q + 1] = v.y;
+        w[4 * q + 2] = v.z;
+        w[4 * q + 3] = v.w;
     }
 }
 
@@ -180,7 +182,8 @@ template <int TWONU, bool COUNT, typename VT, int WPB, bool BATCH>
 __global__ __launch_bounds__(WPB * kWave) void ichol_level(
     const Unit* __restrict__ units, int64_t ubeg, int64_t uend, const int64_t* __restrict__ colptr,
     const int32_t* __restrict__ rowidx, const uint32_t* __restrict__ csc2csr, const int64_t* __restrict__ rowptr,
-    const int64_t* __restrict__ rowend, const int32_t* __restrict__ colidx, VT* __restrict__ Lv,
+    const int64_t* __restrict__ rowend, const int32_t* __restrict__ colidx, const uint32_t* __restrict__ cdelta,
+    const uint32_t* __restrict__ escptr, const int32_t* __restrict__ esc, VT* __restrict__ Lv,
     VT* __restrict__ Lcsc, double* __restrict__ diag, const double* __restrict__ xh, int d, double ell,
     const int32_t* __restrict__ inst, const double* __restrict__ ells, int policy, double tau, int cap,
     unsigned long long* __restrict__ counters) {
@@ -229,37 +232,48 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(
     if (active) {
         const int64_t pend = csc2csr[e];  // position of (k,j) in row k
         int q = 0;
-        // values of one load: FP64 in 16-entry halves, FP32 a whole window (one line each).
-        // Loading all 32 FP64 values at once costs registers, hence occupancy, and
+        // the row's column indices, decoded from the 16-bit gaps: a zero gap is an
+        // escape whose index comes from the row's escape list (first kEscQ in registers)
+        const uint32_t eb = escptr[k], ee = escptr[k + 1];
+        // a queue in named registers (an array would be indexed at run time, in scratch)
+        int e0 = eb < ee ? esc[eb] : 0, e1 = eb + 1 < ee ? esc[eb + 1] : 0;
+        static_assert(kEscQ == 2, "the escape queue below holds 2 entries");
+        uint32_t ec = 0;  // escapes met so far
+        int cur = -1;     // index of the last decoded entry
+        // values of one load: FP64 in 16-entry pieces, FP32 32-entry pieces (one line each).
+        // Loading more FP64 values at once costs registers, hence occupancy, and
         // measured slower; so did 8-entry pieces (more round trips).
-        constexpr int kHalf = sizeof(VT) == 8 ? 16 : kWin;
-        auto merge = [&](const int (&idx)[kWin], const VT (&val)[kHalf], int off, int lim) {
-#pragma unroll
-            for (int t = 0; t < kHalf; ++t) {
-                if (off + t < lim) {
-                    const int i = idx[off + t];
-                    while (sidx[q] < i) ++q;
-                    if (sidx[q] == i) {
-                        const VT lji = sval[q];
-                        if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-val[t], lji, acc);
-                        else acc = __builtin_fmaf(-val[t], lji, acc);
-                        if (COUNT && lji != VT(0)) ++hits;
-                    }
-                }
-            }
-        };
+        constexpr int kPiece = sizeof(VT) == 8 ? 16 : 32;
         for (int64_t p = rowptr[k]; p < pend; p += kWin) {
             const int lim = pend - p < kWin ? int(pend - p) : kWin;  // entries of this window before (k,j)
-            int idx[kWin];
-            load_idx32(colidx, p, idx);
-            VT val[kHalf];
-            load_vals(Lv, p, val);
-            merge(idx, val, 0, lim);
+            uint32_t gw[kWin / 2];
+            load_gaps(cdelta, p, gw);
 #pragma unroll
-            for (int off = kHalf; off < kWin; off += kHalf) {
+            for (int off = 0; off < kWin; off += kPiece) {
                 if (off < lim) {
+                    VT val[kPiece];
                     load_vals(Lv, p + off, val);
-                    merge(idx, val, off, lim);
+#pragma unroll
+                    for (int t = 0; t < kPiece; ++t) {
+                        if (off + t < lim) {
+                            const uint32_t g = (gw[(off + t) >> 1] >> (((off + t) & 1) * 16)) & 0xffffu;
+                            if (g) {
+                                cur += int(g);
+                            } else {
+                                cur = ec < kEscQ ? e0 : esc[eb + ec];
+                                e0 = e1;
+                                ++ec;
+                            }
+                            const int i = cur;
+                            while (sidx[q] < i) ++q;
+                            if (sidx[q] == i) {
+                                const VT lji = sval[q];
+                                if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-val[t], lji, acc);
+                                else acc = __builtin_fmaf(-val[t], lji, acc);
+                                if (COUNT && lji != VT(0)) ++hits;
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -615,7 +629,8 @@ BwdSchedule backward_schedule(const kc::Plan& p) {
 }
 
 struct Layout {
-    size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, L, Lcsc, diag, units, fwd, bshort,
+    size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, cdelta, escptr, esc, L, Lcsc, diag,
+        units, fwd, bshort,
         blong, bchunks, inst, total;
 };
 
@@ -638,6 +653,9 @@ Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
     o.rowptr = take((n + 1) * sizeof(int64_t));
     o.rowend = take(n * sizeof(int64_t));
     o.colidx = take(nnzr * sizeof(int32_t));
+    o.cdelta = take(nnzr * sizeof(uint16_t));
+    o.escptr = take((n + 1) * sizeof(uint32_t));
+    o.esc = take(std::max<size_t>(p.esc.size(), 1) * sizeof(int32_t));
     o.L = take(nnzr * vt);
     o.Lcsc = take(nnz * vt);
     o.diag = take(prec == KC_FP64 ? 0 : n * sizeof(double));
@@ -674,7 +692,8 @@ kc_status launch_level(const kc_factor* f, int tn, bool cnt, int64_t ub, int64_t
     const dim3 grid(grid_for(ue - ub, f->wpb));
     const bool batch = ells != nullptr;
 #define KC_ARGS                                                                                           \
-    f->units, ub, ue, f->colptr, f->rowidx, f->csc2csr, f->rowptr, f->rowend, f->colidx, Lv, Lc, f->diag, \
+    f->units, ub, ue, f->colptr, f->rowidx, f->csc2csr, f->rowptr, f->rowend, f->colidx, f->cdelta, f->escptr, \
+        f->esc, Lv, Lc, f->diag,                                                                          \
         f->xh, f->d, ell, f->inst, ells, pol, tau, f->cap, f->counters
 #define KC_CASE(TN, C)                                                                                    \
     if (tn == TN && cnt == C) {                                                                           \
@@ -978,6 +997,22 @@ kc_status kc_plan_levels(const kc_plan* plan, int32_t* level) {
     return KC_OK;
 }
 
+kc_status kc_plan_set_delta_limit(kc_plan* plan, uint32_t delta_limit, int64_t* nescapes) {
+    if (!plan || delta_limit < 1 || delta_limit > 65536) {
+        kc::set_error("kc_plan_set_delta_limit: need a plan and 1 <= delta_limit <= 65536");
+        return KC_EINVAL;
+    }
+    try {
+        plan->p.delta_limit = delta_limit;
+        kc::encode_row_deltas(plan->p, 0);
+    } catch (const std::bad_alloc&) {
+        kc::set_error("kc_plan_set_delta_limit: out of host memory");
+        return KC_ENOMEM;
+    }
+    if (nescapes) *nescapes = int64_t(plan->p.esc.size());
+    return KC_OK;
+}
+
 void kc_plan_destroy(kc_plan* plan) { delete plan; }
 
 kc_status kc_factor_bytes(const kc_plan* plan, kc_prec prec, size_t* bytes) {
@@ -1038,6 +1073,9 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->rowptr = reinterpret_cast<int64_t*>(base + o.rowptr);
     f->rowend = reinterpret_cast<int64_t*>(base + o.rowend);
     f->colidx = reinterpret_cast<int32_t*>(base + o.colidx);
+    f->cdelta = reinterpret_cast<uint32_t*>(base + o.cdelta);
+    f->escptr = reinterpret_cast<uint32_t*>(base + o.escptr);
+    f->esc = reinterpret_cast<int32_t*>(base + o.esc);
     f->L = base + o.L;
     f->Lcsc = base + o.Lcsc;
     f->diag = prec == KC_MIXED ? reinterpret_cast<double*>(base + o.diag) : nullptr;
@@ -1064,6 +1102,10 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     KC_HIP(hipMemcpyAsync(f->rowptr, p.rowptr.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->rowend, p.rowend.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->colidx, p.colidx.data(), nnzr * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    KC_HIP(hipMemcpyAsync(f->cdelta, p.cdelta.data(), nnzr * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+    KC_HIP(hipMemcpyAsync(f->escptr, p.escptr.data(), (size_t(p.n) + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if (!p.esc.empty())
+        KC_HIP(hipMemcpyAsync(f->esc, p.esc.data(), p.esc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->units, p.units.data(), p.units.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->fwd_rows, p.fwd_rows.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!bs.shortc.empty())

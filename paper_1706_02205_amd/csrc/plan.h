@@ -15,7 +15,7 @@ struct Unit {
     int32_t first;  // offset of the chunk's first entry inside column j
 };
 
-constexpr int kRowAlign = 32;
+constexpr int kRowAlign = 64;
 
 // Backward solve of a long column: one piece of its dot product ...
 struct BwdChunk {
@@ -52,6 +52,15 @@ struct Plan {
     std::vector<int64_t> rowend;    // n: one past the diagonal
     std::vector<int32_t> colidx;
     std::vector<uint32_t> csc2csr;  // CSR position of each CSC entry
+    // the column indices of the padded rows once more, as 16-bit gaps (read by the
+    // factorization): entry t of a row stores colidx[t] - colidx[t-1] (the first
+    // entry colidx + 1, so a gap is never 0); a gap of delta_limit or more is stored
+    // as 0 and the index itself goes to esc -- row k's escapes are
+    // esc[escptr[k] .. escptr[k+1]), in row order.  Padding stores 0.
+    std::vector<uint16_t> cdelta;   // nnz_rows
+    std::vector<uint32_t> escptr;   // n + 1
+    std::vector<int32_t> esc;
+    uint32_t delta_limit = 65536;
 
     // elimination DAG: column j waits for every i < j with (j,i) in S
     std::vector<int32_t> level;     // per column
@@ -90,6 +99,8 @@ void build_schedule(Plan& p, int nthreads);
 void supernodal_transform(Plan& p, int nthreads);
 // Block-diagonal union of independently analysed instances.
 void merge_plans(const std::vector<Plan>& parts, Plan& out);
+// (Re)builds cdelta / escptr / esc from colidx with p.delta_limit.
+void encode_row_deltas(Plan& p, int nthreads);
 
 // Thread-local error message shared by the C ABI.
 void set_error(const std::string& msg);

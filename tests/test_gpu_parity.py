@@ -73,6 +73,34 @@ def test_factor_bitwise_equal_to_oracle(K, case):
     assert bad.size == 0, f"{bad.size} of {L.size} entries of L differ; first at CSC position {bad[:5]}"
 
 
+@pytest.mark.parametrize("limit", [1, 3, 40, 65536])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_index_gap_escapes_do_not_change_the_factor(K, limit, prec):
+    """The factorization reads row indices as 16-bit gaps with an escape list for wide gaps.
+    Lowering the gap limit forces escapes -- every entry at limit 1, more than the two a row
+    keeps in registers at limits 1 and 3 -- and the factor must stay bitwise the same."""
+    print(f"[gpu] index gap escapes limit={limit} prec={prec}", flush=True)
+    w = W.small_uniform_2d()
+    plan = K.analyze(w.points, w.rho)
+    xd = dev(w.points)
+    pivot, tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
+    f0 = K.Factor(plan, prec)
+    f0.factorize(xd, w.nu, w.lengthscale, pivot, tau)
+    ref = f0.export_L()
+    nesc = plan.set_delta_limit(limit)
+    if limit == 1:
+        assert nesc == plan.nnz
+    if limit <= 3:
+        assert nesc > 8 * plan.n  # most rows go beyond the register queue
+    f = K.Factor(plan, prec)
+    f.factorize(xd, w.nu, w.lengthscale, pivot, tau)
+    assert np.array_equal(f.export_L(), ref)
+    if prec == "fp64":
+        P = O.pattern(w.points, w.rho)
+        R = O.ichol(P, O.theta_on_pattern(P, w.nu, w.lengthscale), O.PIVOT_ZERO)
+        assert np.array_equal(f.export_L(), R.L)
+
+
 def test_factor_is_deterministic(K):
     print("[gpu] determinism", flush=True)
     w = W.small_uniform_2d()
