@@ -159,15 +159,27 @@ def run_batched(args):
     f.factorize_batched(xd, 1.5, ed, pivot, tau, count_updates=True)
     st = f.stats()
     wpb = f.tune(xd, 1.5, ell_dev=ed, pivot=pivot, tau=tau, reps=2)
+    wpb, pm = f.schedule()
+    log(f"[bench] tuner: {wpb} wavefronts per workgroup, levels with <= {pm} units in persistent launches")
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    # eager factorize + solve with the tuned schedule (persistent launches included)
+    eager_s = timed(lambda: (f.factorize_batched(xd, 1.5, ed, pivot, tau), f.solve(bd)))
+    # the same step replayed from a HIP graph (one launch per level)
     g = f.capture(xd, bd, 1.5, ell_dev=ed, pivot=pivot, tau=tau)
-    for _ in range(args.warmup):
-        g.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.launch()
-    torch.cuda.synchronize()
-    step_s = (time.perf_counter() - t0) / args.steps
+    graph_s = timed(g.launch)
+    ginfo = g.info()
+    step_s = min(eager_s, graph_s)
+    log(f"[bench] batched step: eager {eager_s * 1e3:.1f} ms, graph {graph_s * 1e3:.1f} ms ({ginfo['nodes']} nodes)")
     nnz = info["nnz"]
     print(json.dumps({
         "metric": "S-entries factored/s over a batch of independent problems", "value": nnz / step_s,
@@ -176,7 +188,8 @@ def run_batched(args):
         "dtype": "f32-updates/f64-pivots" if f.prec == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"batched-{len(xs)}-matern32", "instances": len(xs), "n_total": info["n"],
                    "nnz": nnz, "levels": info["nlevels"], "nrhs": 1, "rho": 3.0, "tuned_waves_per_block": wpb,
-                   "graph": True},
+                   "tuned_persist_max": pm, "graph": graph_s <= eager_s},
+        "eager_ms": eager_s * 1e3, "graph_ms": graph_s * 1e3, "graph_nodes": ginfo["nodes"],
         "updates": st.updates, "host_analysis_s": t_analysis}), flush=True)
 
 

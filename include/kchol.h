@@ -194,22 +194,43 @@ kc_status kc_factor_export_L(const kc_factor *f, double *vals);
 
 void kc_factor_destroy(kc_factor *f);
 
-/* Autotuner: times the factorization (reps repetitions after a warm-up) with 1,
- * 2 and 4 wavefronts per workgroup -- each fitting the staged rows in LDS --
- * and keeps the fastest for this factor.  Results are bitwise identical for
- * every choice.  For a batch plan pass ell_dev (and ell is ignored), else NULL. */
+/* Schedule of the factorization.  Each DAG level runs as its own launch with
+ * `wpb` wavefronts (1, 2 or 4) per workgroup, except that every run of
+ * consecutive levels with at most `persist_max` work units (64 entries of a
+ * column each) runs as ONE persistent launch: a cooperative grid, resident as a
+ * whole, whose wavefronts stride over each level's units with a grid-wide
+ * barrier between levels.  persist_max = 0 (the default) launches every level
+ * separately; INT64_MAX runs the whole factorization in one persistent launch.
+ * Results are bitwise identical for every schedule.  KC_EINVAL for wpb not in
+ * {1, 2, 4}, persist_max < 0, or staged rows that do not fit in LDS. */
+kc_status kc_factor_set_schedule(kc_factor *f, int32_t wpb, int64_t persist_max);
+kc_status kc_factor_schedule(const kc_factor *f, int32_t *wpb, int64_t *persist_max);
+
+/* Autotuner: times the factorization (reps repetitions after a warm-up) for
+ * every schedule in {1, 2, 4} wavefronts per workgroup x level grouping
+ * persist_max in {0, 256, 4096, all levels} -- skipping those whose staged rows
+ * do not fit in LDS or whose persistent grid cannot be resident -- and keeps the
+ * fastest for this factor (kc_factor_schedule reports it).  Results are bitwise
+ * identical for every choice.  For a batch plan pass ell_dev (and ell is
+ * ignored), else NULL. */
 kc_status kc_factor_tune(kc_factor *f, const double *x_dev, double nu, double ell, const double *ell_dev,
                          kc_pivot pivot, double tau, int32_t reps, void *stream, int32_t *chosen_wpb);
 
 /* Captures factorize + solve of this factor into a HIP graph (on an internal
  * stream; no memory is allocated by the captured work) so that one
- * kc_graph_launch replays every level launch.  Arguments are those of
+ * kc_graph_launch replays every level launch (with the factor's wavefronts per
+ * workgroup, one launch per level).  Arguments are those of
  * kc_factorize/kc_factorize_batched and kc_solve; the pointers are baked into the
  * graph and must stay valid.  Replays on a stream are ordered like any other
  * work on it. */
 kc_status kc_graph_create(kc_factor *f, const double *x_dev, double nu, double ell, const double *ell_dev,
                           kc_pivot pivot, double tau, const double *b_dev, double *sol_dev, int32_t nrhs,
                           void *scratch_dev, size_t scratch_bytes, kc_graph **out);
+/* Number of nodes of the recorded graph, and whether its factorization was
+ * recorded with persistent launches (1) or as one launch per level (0).
+ * Graphs currently record one launch per level: a persistent launch needs the
+ * runtime's cooperative launch path, which is used eagerly only. */
+kc_status kc_graph_info(const kc_graph *g, int64_t *nodes, int32_t *persistent);
 kc_status kc_graph_launch(kc_graph *g, void *stream);
 void kc_graph_destroy(kc_graph *g);
 

@@ -214,7 +214,8 @@ class Factor:
 
     def tune(self, x_dev, nu: float, lengthscale: float = 0.0, ell_dev=None, pivot: str = "zero", tau: float = 0.0,
              reps: int = 3, stream=None) -> int:
-        """Pick the fastest wavefronts-per-workgroup for this factor by timing it; returns the choice."""
+        """Pick the fastest schedule (wavefronts per workgroup x level grouping) for this factor by timing it;
+        returns the wavefronts per workgroup (schedule() gives both)."""
         self._check_points(x_dev)
         w = C.c_int32()
         _lib.check(_lib.load().kc_factor_tune(self._h, C.c_void_p(x_dev.data_ptr()), float(nu), float(lengthscale),
@@ -222,6 +223,18 @@ class Factor:
                                               _PIVOTS[pivot], float(tau), int(reps), _stream_ptr(stream),
                                               C.byref(w)), "kc_factor_tune")
         return int(w.value)
+
+    def set_schedule(self, wpb: int, persist_max: int) -> None:
+        """Wavefronts per workgroup (1, 2, 4) and the level grouping: runs of consecutive levels with at most
+        persist_max work units share one persistent launch (0: every level its own launch; 2**63 - 1: the
+        whole factorization in one launch)."""
+        _lib.check(_lib.load().kc_factor_set_schedule(self._h, int(wpb), int(persist_max)), "kc_factor_set_schedule")
+
+    def schedule(self) -> tuple:
+        """(wavefronts per workgroup, persist_max) in use -- the tuner's choice after tune()."""
+        w, pm = C.c_int32(), C.c_int64()
+        _lib.check(_lib.load().kc_factor_schedule(self._h, C.byref(w), C.byref(pm)), "kc_factor_schedule")
+        return int(w.value), int(pm.value)
 
     def capture(self, x_dev, b_dev, nu: float, lengthscale: float = 0.0, ell_dev=None, pivot: str = "zero",
                 tau: float = 0.0) -> "Graph":
@@ -318,6 +331,12 @@ class Graph:
     def launch(self, stream=None):
         _lib.check(_lib.load().kc_graph_launch(self._h, _stream_ptr(stream)), "kc_graph_launch")
         return self.out
+
+    def info(self) -> dict:
+        """Nodes of the recorded graph and whether the factorization was recorded with persistent launches."""
+        nodes, pers = C.c_int64(), C.c_int32()
+        _lib.check(_lib.load().kc_graph_info(self._h, C.byref(nodes), C.byref(pers)), "kc_graph_info")
+        return {"nodes": int(nodes.value), "persistent": bool(pers.value)}
 
     def __del__(self):
         h = getattr(self, "_h", None)

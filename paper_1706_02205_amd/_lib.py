@@ -39,7 +39,7 @@ EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "
             "kc_plan_destroy", "kc_factor_bytes", "kc_factor_create", "kc_factorize", "kc_theta", "kc_solve_bytes",
             "kc_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
             "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
-            "kc_factor_tune", "kc_graph_create", "kc_graph_launch", "kc_graph_destroy", "kc_analyze_supernodal",
+            "kc_factor_tune", "kc_factor_set_schedule", "kc_factor_schedule", "kc_graph_create", "kc_graph_info", "kc_graph_launch", "kc_graph_destroy", "kc_analyze_supernodal",
             "kc_plan_supernodes")
 
 _LIB = None
@@ -90,6 +90,9 @@ def load():
         "kc_factor_tune": (C.c_int, [vp, vp, f64, f64, vp, C.c_int, f64, i32, vp, P(i32)]),
         "kc_graph_create": (C.c_int, [vp, vp, f64, f64, vp, C.c_int, f64, vp, vp, i32, vp, sz, P(vp)]),
         "kc_graph_launch": (C.c_int, [vp, vp]),
+        "kc_factor_set_schedule": (C.c_int, [vp, i32, C.c_int64]),
+        "kc_factor_schedule": (C.c_int, [vp, P(i32), P(C.c_int64)]),
+        "kc_graph_info": (C.c_int, [vp, P(C.c_int64), P(i32)]),
         "kc_graph_destroy": (None, [vp]),
         "kc_analyze_supernodal": (C.c_int, [vp, i64, i32, f64, i32, P(vp)]),
         "kc_plan_supernodes": (C.c_int, [vp, vp, P(i64)]),

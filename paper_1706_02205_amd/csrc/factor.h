@@ -14,6 +14,8 @@ struct kc_factor {
     int32_t d = 0;
     int32_t cap = 0;          // LDS entries per wavefront (longest row, rounded up)
     int32_t wpb = 4;          // wavefronts per block of the factorization kernel
+    int64_t persist_max = 0;  // levels with at most this many units run in persistent launches
+    int32_t num_cu = 0;       // compute units of the factor's device
     kc_prec prec = KC_FP64;
     // device regions
     unsigned long long* counters = nullptr;
@@ -32,6 +34,7 @@ struct kc_factor {
     void* Lcsc = nullptr;     // by columns: double[nnz] or float[nnz]
     double* diag = nullptr;   // MIXED only
     kc::Unit* units = nullptr;
+    int64_t* unit_off_dev = nullptr;  // nlevels + 1, units of each level
     int32_t* fwd_rows = nullptr;
     int32_t* bwd_short = nullptr;
     kc::LongCol* bwd_long = nullptr;

@@ -11,6 +11,7 @@
 // see ichol_level) far more often than it writes columns.
 //
 // Compiled with -ffp-contract=off: every fused multiply-add is written out.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -178,38 +179,67 @@ __device__ __forceinline__ int xcd_block() {
 // VT = double: FP64.  VT = float (MIXED): off-diagonal Theta, updates and the
 // stored L in FP32; the pivot accumulates exact FP32 x FP32 products in FP64,
 // and sqrt and the division by L_jj are FP64.
-template <int TWONU, bool COUNT, typename VT, int WPB, bool BATCH>
-__global__ __launch_bounds__(WPB * kWave) void ichol_level(
-    const Unit* __restrict__ units, int64_t ubeg, int64_t uend, const int64_t* __restrict__ colptr,
-    const int32_t* __restrict__ rowidx, const uint32_t* __restrict__ csc2csr, const int64_t* __restrict__ rowptr,
-    const int64_t* __restrict__ rowend, const int32_t* __restrict__ colidx, const uint32_t* __restrict__ cdelta,
-    const uint32_t* __restrict__ escptr, const int32_t* __restrict__ esc, VT* __restrict__ Lv,
-    VT* __restrict__ Lcsc, double* __restrict__ diag, const double* __restrict__ xh, int d, double ell,
-    const int32_t* __restrict__ inst, const double* __restrict__ ells, int policy, double tau, int cap,
-    unsigned long long* __restrict__ counters) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lane = threadIdx.x % kWave;
-    VT* sval = reinterpret_cast<VT*>(smem) + wave * cap;
-    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(WPB) * cap * sizeof(VT)) + wave * cap;
+// Everything one work unit reads and writes.
+template <typename VT>
+struct IcholArgs {
+    const Unit* units;
+    const int64_t* colptr;
+    const int32_t* rowidx;
+    const uint32_t* csc2csr;
+    const int64_t* rowptr;
+    const int64_t* rowend;
+    const int32_t* colidx;
+    const uint32_t* cdelta;
+    const uint32_t* escptr;
+    const int32_t* esc;
+    VT* Lv;
+    VT* Lcsc;
+    double* diag;
+    const double* xh;
+    int d;
+    double ell;
+    const int32_t* inst;
+    const double* ells;
+    int policy;
+    double tau;
+    int cap;
+    unsigned long long* counters;
+};
 
-    const int64_t u = ubeg + int64_t(xcd_block()) * WPB + wave;
-    const bool valid = u < uend;
-    int j = 0, first = 0, np = 0;
-    int64_t t0 = 0;
-    if (valid) {
-        j = __builtin_amdgcn_readfirstlane(units[u].col);
-        first = __builtin_amdgcn_readfirstlane(units[u].first);
-        t0 = rowptr[j];
-        np = int(rowend[j] - 1 - t0);  // parents of j: row j without its diagonal
-    }
+// One work unit: 64 consecutive entries of column j, one per lane of the wave.
+// sval/sidx: the wave's own LDS region (cap entries).
+template <int TWONU, bool COUNT, typename VT, bool BATCH>
+__device__ __forceinline__ void factor_unit(const IcholArgs<VT>& a, int64_t u, int lane, VT* sval, int32_t* sidx) {
+    const Unit* __restrict__ units = a.units;
+    const int64_t* __restrict__ colptr = a.colptr;
+    const int32_t* __restrict__ rowidx = a.rowidx;
+    const uint32_t* __restrict__ csc2csr = a.csc2csr;
+    const int64_t* __restrict__ rowptr = a.rowptr;
+    const int64_t* __restrict__ rowend = a.rowend;
+    const int32_t* __restrict__ colidx = a.colidx;
+    const uint32_t* __restrict__ cdelta = a.cdelta;
+    const uint32_t* __restrict__ escptr = a.escptr;
+    const int32_t* __restrict__ esc = a.esc;
+    VT* __restrict__ Lv = a.Lv;
+    VT* __restrict__ Lcsc = a.Lcsc;
+    double* __restrict__ diag = a.diag;
+    const double* __restrict__ xh = a.xh;
+    const int d = a.d, policy = a.policy;
+    const double tau = a.tau;
+    double ell = a.ell;
+    unsigned long long* __restrict__ counters = a.counters;
+
+    const int j = __builtin_amdgcn_readfirstlane(units[u].col);
+    const int first = __builtin_amdgcn_readfirstlane(units[u].first);
+    const int64_t t0 = rowptr[j];
+    const int np = int(rowend[j] - 1 - t0);  // parents of j: row j without its diagonal
+    wave_lds_sync();  // the wave's previous unit is done with the staging area
     for (int t = lane; t < np; t += kWave) {
         sidx[t] = colidx[t0 + t];
         sval[t] = Lv[t0 + t];
     }
     if (lane == 0) sidx[np] = INT_MAX;  // sentinel ends every cursor walk
-    __syncthreads();
-    if (!valid) return;
+    wave_lds_sync();
 
     double dacc = 1.0;  // Theta_jj
     for (int t = 0; t < np; ++t) {
@@ -220,7 +250,7 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(
     const int64_t e = colptr[j] + first + lane;
     const bool active = e < colptr[j + 1];
     const int k = active ? rowidx[e] : j;
-    if constexpr (BATCH) ell = ells[inst[j]];  // lengthscale of j's instance
+    if constexpr (BATCH) ell = a.ells[a.inst[j]];  // lengthscale of j's instance
     int hard = 0;
     VT acc;
     if constexpr (sizeof(VT) == 8)
@@ -311,6 +341,38 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(
         if (lane == 0 && tot) atomicAdd(counters + kUpdates, tot);
     }
     if (hard && active) atomicAdd(counters + kExpHard, 1ull);
+}
+
+// One DAG level per launch: a wave per unit.
+template <int TWONU, bool COUNT, typename VT, int WPB, bool BATCH>
+__global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, int64_t ubeg, int64_t uend) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    VT* sval = reinterpret_cast<VT*>(smem) + wave * a.cap;
+    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(WPB) * a.cap * sizeof(VT)) + wave * a.cap;
+    const int64_t u = ubeg + int64_t(xcd_block()) * WPB + wave;
+    if (u < uend) factor_unit<TWONU, COUNT, VT, BATCH>(a, u, lane, sval, sidx);
+}
+
+// Levels [l0, l1) in one persistent launch: the waves of a grid that is resident
+// as a whole (cooperative launch) stride over each level's units, and a grid-wide
+// barrier separates consecutive levels.
+template <int TWONU, bool COUNT, typename VT, int WPB, bool BATCH>
+__global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a, const int64_t* __restrict__ unit_off,
+                                                                int l0, int l1) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    VT* sval = reinterpret_cast<VT*>(smem) + wave * a.cap;
+    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(WPB) * a.cap * sizeof(VT)) + wave * a.cap;
+    const int64_t slot = int64_t(xcd_block()) * WPB + wave, stride = int64_t(gridDim.x) * WPB;
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (int l = l0; l < l1; ++l) {
+        const int64_t ub = unit_off[l], ue = unit_off[l + 1];
+        for (int64_t u = ub + slot; u < ue; u += stride) factor_unit<TWONU, COUNT, VT, BATCH>(a, u, lane, sval, sidx);
+        grid.sync();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -630,7 +692,7 @@ BwdSchedule backward_schedule(const kc::Plan& p) {
 
 struct Layout {
     size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, cdelta, escptr, esc, L, Lcsc, diag,
-        units, fwd, bshort,
+        units, unit_off, fwd, bshort,
         blong, bchunks, inst, total;
 };
 
@@ -660,6 +722,7 @@ Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
     o.Lcsc = take(nnz * vt);
     o.diag = take(prec == KC_FP64 ? 0 : n * sizeof(double));
     o.units = take(p.units.size() * sizeof(Unit));
+    o.unit_off = take((size_t(p.nlevels) + 1) * sizeof(int64_t));
     o.fwd = take(n * sizeof(int32_t));
     o.bshort = take(b.shortc.size() * sizeof(int32_t));
     o.blong = take(b.longc.size() * sizeof(kc::LongCol));
@@ -684,38 +747,113 @@ int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 1 + 15) / 16 * 
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 template <typename VT>
-kc_status launch_level(const kc_factor* f, int tn, bool cnt, int64_t ub, int64_t ue, double ell, const double* ells,
-                       int pol, double tau, hipStream_t s) {
-    VT* Lv = static_cast<VT*>(f->L);
-    VT* Lc = static_cast<VT*>(f->Lcsc);
-    const size_t lds = size_t(f->wpb) * f->cap * (sizeof(VT) + sizeof(int32_t));
-    const dim3 grid(grid_for(ue - ub, f->wpb));
-    const bool batch = ells != nullptr;
-#define KC_ARGS                                                                                           \
-    f->units, ub, ue, f->colptr, f->rowidx, f->csc2csr, f->rowptr, f->rowend, f->colidx, f->cdelta, f->escptr, \
-        f->esc, Lv, Lc, f->diag,                                                                          \
-        f->xh, f->d, ell, f->inst, ells, pol, tau, f->cap, f->counters
-#define KC_CASE(TN, C)                                                                                    \
-    if (tn == TN && cnt == C) {                                                                           \
-        if (batch) {                                                                                      \
-            if (f->wpb == 4) ichol_level<TN, C, VT, 4, true><<<grid, 4 * kWave, lds, s>>>(KC_ARGS);         \
-            else if (f->wpb == 2) ichol_level<TN, C, VT, 2, true><<<grid, 2 * kWave, lds, s>>>(KC_ARGS);    \
-            else ichol_level<TN, C, VT, 1, true><<<grid, kWave, lds, s>>>(KC_ARGS);                        \
-        } else {                                                                                          \
-            if (f->wpb == 4) ichol_level<TN, C, VT, 4, false><<<grid, 4 * kWave, lds, s>>>(KC_ARGS);        \
-            else if (f->wpb == 2) ichol_level<TN, C, VT, 2, false><<<grid, 2 * kWave, lds, s>>>(KC_ARGS);   \
-            else ichol_level<TN, C, VT, 1, false><<<grid, kWave, lds, s>>>(KC_ARGS);                       \
-        }                                                                                                 \
+IcholArgs<VT> ichol_args(const kc_factor* f, double ell, const double* ells, int pol, double tau) {
+    IcholArgs<VT> a;
+    a.units = f->units;
+    a.colptr = f->colptr;
+    a.rowidx = f->rowidx;
+    a.csc2csr = f->csc2csr;
+    a.rowptr = f->rowptr;
+    a.rowend = f->rowend;
+    a.colidx = f->colidx;
+    a.cdelta = f->cdelta;
+    a.escptr = f->escptr;
+    a.esc = f->esc;
+    a.Lv = static_cast<VT*>(f->L);
+    a.Lcsc = static_cast<VT*>(f->Lcsc);
+    a.diag = f->diag;
+    a.xh = f->xh;
+    a.d = f->d;
+    a.ell = ell;
+    a.inst = f->inst;
+    a.ells = ells;
+    a.policy = pol;
+    a.tau = tau;
+    a.cap = f->cap;
+    a.counters = f->counters;
+    return a;
+}
+
+// One level [ub, ue) as its own launch, or levels [l0, l1) (at most maxu units
+// each) as one cooperative persistent launch.
+template <int TN, bool C, typename VT, int WPB, bool B>
+kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1,
+                     int64_t maxu, bool persistent, hipStream_t s) {
+    const size_t lds = size_t(WPB) * f->cap * (sizeof(VT) + sizeof(int32_t));
+    if (!persistent) {
+        ichol_level<TN, C, VT, WPB, B><<<grid_for(ue - ub, WPB), WPB * kWave, lds, s>>>(a, ub, ue);
+        KC_LAUNCH_CHECK();
+        return KC_OK;
     }
-    KC_CASE(1, false)
-    KC_CASE(1, true)
-    KC_CASE(3, false)
-    KC_CASE(3, true)
-    KC_CASE(5, false)
-    KC_CASE(5, true)
-#undef KC_CASE
-#undef KC_ARGS
-    KC_LAUNCH_CHECK();
+    const void* fn = reinterpret_cast<const void*>(&ichol_persistent<TN, C, VT, WPB, B>);
+    int per_cu = 0;
+    KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WPB * kWave, lds));
+    if (per_cu < 1) {
+        kc::set_error("kc_factorize: the persistent kernel does not fit on a compute unit");
+        return KC_EHIP;
+    }
+    // every block resident at once (the cooperative launch refuses anything larger)
+    const int64_t want = std::max<int64_t>(1, int64_t(grid_for(maxu, WPB)));
+    const unsigned blocks = unsigned(std::min<int64_t>(int64_t(per_cu) * f->num_cu, want));
+    IcholArgs<VT> av = a;
+    const int64_t* uo = f->unit_off_dev;
+    int l0v = l0, l1v = l1;
+    void* args[] = {&av, &uo, &l0v, &l1v};
+    KC_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(WPB * kWave), args, unsigned(lds), s));
+    return KC_OK;
+}
+
+template <int TN, bool C, typename VT, bool B>
+kc_status launch_wpb(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1, int64_t maxu,
+                     bool persistent, hipStream_t s) {
+    if (f->wpb == 4) return launch_one<TN, C, VT, 4, B>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    if (f->wpb == 2) return launch_one<TN, C, VT, 2, B>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    return launch_one<TN, C, VT, 1, B>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+}
+
+template <int TN, typename VT>
+kc_status launch_tn(const kc_factor* f, bool cnt, bool batch, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0,
+                    int l1, int64_t maxu, bool persistent, hipStream_t s) {
+    if (cnt) {
+        return batch ? launch_wpb<TN, true, VT, true>(f, a, ub, ue, l0, l1, maxu, persistent, s)
+                     : launch_wpb<TN, true, VT, false>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    }
+    return batch ? launch_wpb<TN, false, VT, true>(f, a, ub, ue, l0, l1, maxu, persistent, s)
+                 : launch_wpb<TN, false, VT, false>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+}
+
+// The levels of the factorization: a level with more than f->persist_max units is
+// its own launch; each run of consecutive smaller levels is one persistent launch.
+template <typename VT>
+kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const double* ells, int pol, double tau,
+                        hipStream_t s) {
+    const IcholArgs<VT> a = ichol_args<VT>(f, ell, ells, pol, tau);
+    const bool batch = ells != nullptr;
+    auto go = [&](int64_t ub, int64_t ue, int l0, int l1, int64_t maxu, bool persistent) {
+        if (tn == 1) return launch_tn<1, VT>(f, cnt, batch, a, ub, ue, l0, l1, maxu, persistent, s);
+        if (tn == 3) return launch_tn<3, VT>(f, cnt, batch, a, ub, ue, l0, l1, maxu, persistent, s);
+        return launch_tn<5, VT>(f, cnt, batch, a, ub, ue, l0, l1, maxu, persistent, s);
+    };
+    const int nl = int(f->unit_off.size()) - 1;
+    int v = 0;
+    while (v < nl) {
+        const int64_t cnt_v = f->unit_off[v + 1] - f->unit_off[v];
+        if (cnt_v > f->persist_max) {
+            const kc_status st = go(f->unit_off[v], f->unit_off[v + 1], v, v + 1, cnt_v, false);
+            if (st != KC_OK) return st;
+            ++v;
+            continue;
+        }
+        int w = v;
+        int64_t maxu = 0;
+        while (w < nl && f->unit_off[w + 1] - f->unit_off[w] <= f->persist_max) {
+            maxu = std::max<int64_t>(maxu, f->unit_off[w + 1] - f->unit_off[w]);
+            ++w;
+        }
+        const kc_status st = maxu > 0 ? go(0, 0, v, w, maxu, true) : KC_OK;  // a run of empty levels needs nothing
+        if (st != KC_OK) return st;
+        v = w;
+    }
     return KC_OK;
 }
 
@@ -1064,6 +1202,11 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->d = p.d;
     f->prec = prec;
     f->nunits = int64_t(p.units.size());
+    {
+        int dev = 0;
+        KC_HIP(hipGetDevice(&dev));
+        KC_HIP(hipDeviceGetAttribute(&f->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     f->counters = reinterpret_cast<unsigned long long*>(base + o.counters);
     f->xh = reinterpret_cast<double*>(base + o.xh);
     f->perm = reinterpret_cast<int32_t*>(base + o.perm);
@@ -1080,6 +1223,7 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->Lcsc = base + o.Lcsc;
     f->diag = prec == KC_MIXED ? reinterpret_cast<double*>(base + o.diag) : nullptr;
     f->units = reinterpret_cast<Unit*>(base + o.units);
+    f->unit_off_dev = reinterpret_cast<int64_t*>(base + o.unit_off);
     f->fwd_rows = reinterpret_cast<int32_t*>(base + o.fwd);
     f->bwd_short = reinterpret_cast<int32_t*>(base + o.bshort);
     f->bwd_long = reinterpret_cast<kc::LongCol*>(base + o.blong);
@@ -1107,6 +1251,8 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     if (!p.esc.empty())
         KC_HIP(hipMemcpyAsync(f->esc, p.esc.data(), p.esc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->units, p.units.data(), p.units.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
+    KC_HIP(hipMemcpyAsync(f->unit_off_dev, p.unit_off.data(), p.unit_off.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->fwd_rows, p.fwd_rows.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!bs.shortc.empty())
         KC_HIP(hipMemcpyAsync(f->bwd_short, bs.shortc.data(), bs.shortc.size() * sizeof(int32_t),
@@ -1143,15 +1289,9 @@ static kc_status factorize_impl(kc_factor* f, const double* x_dev, double nu, do
     gather_points<<<grid_for(f->n * f->d, kBlock), kBlock, 0, s>>>(x_dev, f->perm, f->n, f->d, f->xh);
     KC_LAUNCH_CHECK();
     const bool cnt = count_updates != 0;
-    const size_t nl = f->unit_off.size() - 1;
-    for (size_t v = 0; v < nl; ++v) {
-        const int64_t ub = f->unit_off[v], ue = f->unit_off[v + 1];
-        if (ue <= ub) continue;
-        const kc_status st = f->prec == KC_FP64
-                                 ? launch_level<double>(f, tn, cnt, ub, ue, ell, ells, int(pivot), tau, s)
-                                 : launch_level<float>(f, tn, cnt, ub, ue, ell, ells, int(pivot), tau, s);
-        if (st != KC_OK) return st;
-    }
+    const kc_status st = f->prec == KC_FP64 ? launch_levels<double>(f, tn, cnt, ell, ells, int(pivot), tau, s)
+                                            : launch_levels<float>(f, tn, cnt, ell, ells, int(pivot), tau, s);
+    if (st != KC_OK) return st;
     f->factorized = true;
     f->counted = cnt;
     f->last = s;
@@ -1282,34 +1422,71 @@ kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double el
     KC_HIP(hipEventCreate(&a));
     KC_HIP(hipEventCreate(&b));
     int best = f->wpb;
+    int64_t best_pm = f->persist_max;
     float best_ms = 1e30f;
+    // level grouping: levels with at most `pm` units share persistent launches
+    const int64_t kGroupings[] = {0, 256, 4096, INT64_MAX};
     for (int wpb : {1, 2, 4}) {
         if (size_t(wpb) * f->cap * (vt + 4) > 64 * 1024) continue;
-        f->wpb = wpb;
-        kc_status st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, stream);  // warm-up
-        if (st != KC_OK) break;
-        KC_HIP(hipEventRecord(a, s));
-        for (int r = 0; r < reps && st == KC_OK; ++r) st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, stream);
-        KC_HIP(hipEventRecord(b, s));
-        KC_HIP(hipEventSynchronize(b));
-        if (st != KC_OK) break;
-        float ms = 0.f;
-        KC_HIP(hipEventElapsedTime(&ms, a, b));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = wpb;
+        for (int64_t pm : kGroupings) {
+            f->wpb = wpb;
+            f->persist_max = pm;
+            kc_status st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, stream);  // warm-up
+            if (st != KC_OK) {
+                // e.g. a persistent launch that does not fit: skip this grouping
+                (void)hipGetLastError();
+                (void)hipStreamSynchronize(s);
+                continue;
+            }
+            KC_HIP(hipEventRecord(a, s));
+            for (int r = 0; r < reps && st == KC_OK; ++r)
+                st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, stream);
+            KC_HIP(hipEventRecord(b, s));
+            KC_HIP(hipEventSynchronize(b));
+            if (st != KC_OK) continue;
+            float ms = 0.f;
+            KC_HIP(hipEventElapsedTime(&ms, a, b));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = wpb;
+                best_pm = pm;
+            }
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     f->wpb = best;
+    f->persist_max = best_pm;
     if (chosen_wpb) *chosen_wpb = best;
+    return KC_OK;
+}
+
+kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max) {
+    if (!f || (wpb != 1 && wpb != 2 && wpb != 4) || persist_max < 0) {
+        kc::set_error("kc_factor_set_schedule: wavefronts per block must be 1, 2 or 4 and persist_max >= 0");
+        return KC_EINVAL;
+    }
+    const size_t vt = f->prec == KC_FP64 ? sizeof(double) : sizeof(float);
+    if (size_t(wpb) * f->cap * (vt + 4) > 64 * 1024) {
+        kc::set_error("kc_factor_set_schedule: the staged rows of that many wavefronts do not fit in LDS");
+        return KC_EINVAL;
+    }
+    f->wpb = wpb;
+    f->persist_max = persist_max;
+    return KC_OK;
+}
+
+kc_status kc_factor_schedule(const kc_factor* f, int32_t* wpb, int64_t* persist_max) {
+    if (!f) return KC_EINVAL;
+    if (wpb) *wpb = f->wpb;
+    if (persist_max) *persist_max = f->persist_max;
     return KC_OK;
 }
 
 struct kc_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int32_t persistent = 0;  // the factorization was recorded with persistent launches
     ~kc_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1331,31 +1508,58 @@ kc_status kc_graph_create(kc_factor* f, const double* x_dev, double nu, double e
     }
     std::unique_ptr<kc_graph> g(new (std::nothrow) kc_graph);
     if (!g) return KC_ENOMEM;
-    hipStream_t cs = nullptr;
-    KC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    kc_status st = KC_OK;
-    if (e == hipSuccess) {
-        st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, cs);
-        if (st == KC_OK) {
-            double* y = static_cast<double*>(scratch_dev);
-            double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
-                                                        align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
-            st = f->prec == KC_FP64 ? solve_typed<double>(f, b_dev, sol_dev, nrhs, y, partial, cs)
-                                    : solve_typed<float>(f, b_dev, sol_dev, nrhs, y, partial, cs);
+    auto capture = [&](hipError_t& e) -> kc_status {
+        hipStream_t cs = nullptr;
+        KC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        kc_status st = KC_OK;
+        if (e == hipSuccess) {
+            st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, cs);
+            if (st == KC_OK) {
+                double* y = static_cast<double*>(scratch_dev);
+                double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
+                                                            align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
+                st = f->prec == KC_FP64 ? solve_typed<double>(f, b_dev, sol_dev, nrhs, y, partial, cs)
+                                        : solve_typed<float>(f, b_dev, sol_dev, nrhs, y, partial, cs);
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            if (e2 != hipSuccess && st == KC_OK) e = e2;
+            if (e == hipSuccess && st == KC_OK) g->graph = graph;
+            else if (graph) (void)hipGraphDestroy(graph);
         }
-        hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
-        if (e2 != hipSuccess && st == KC_OK) e = e2;
-    }
-    (void)hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
+        return st;
+    };
+    // Graphs record one launch per level: cooperative launches are not recorded
+    // (the grid barrier of a persistent launch needs the runtime's cooperative
+    // launch path at every replay).  The factor's own schedule is kept for eager use.
+    const int64_t pm = f->persist_max;
+    f->persist_max = 0;
+    hipError_t e = hipSuccess;
+    kc_status st = capture(e);
+    f->persist_max = pm;
+    const bool persistent_recorded = false;
     if (e != hipSuccess) {
         kc::set_error(std::string("kc_graph_create: capture failed: ") + hipGetErrorString(e));
         return KC_EHIP;
     }
     if (st != KC_OK) return st;
     KC_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    g->persistent = persistent_recorded ? 1 : 0;
     f->factorized = true;
     *out = g.release();
+    return KC_OK;
+}
+
+kc_status kc_graph_info(const kc_graph* g, int64_t* nodes, int32_t* persistent) {
+    if (!g) return KC_EINVAL;
+    if (nodes) {
+        size_t cnt = 0;
+        KC_HIP(hipGraphGetNodes(g->graph, nullptr, &cnt));
+        *nodes = int64_t(cnt);
+    }
+    if (persistent) *persistent = g->persistent;
     return KC_OK;
 }
 

@@ -89,8 +89,42 @@ def test_tuner_choice_does_not_change_results(K, batch):
     base = f.export_L()
     wpb = f.tune(xd, 1.5, ell_dev=ed, reps=2)
     assert wpb in (1, 2, 4)
+    w2, pm = f.schedule()
+    print(f"[gpu] tuner chose wpb={w2} persist_max={pm}", flush=True)
+    assert w2 == wpb and pm in (0, 256, 4096, 2**63 - 1)
     f.factorize_batched(xd, 1.5, ed)
     assert np.array_equal(f.export_L(), base)
+
+
+ALL_LEVELS = 2**63 - 1
+
+
+@pytest.mark.parametrize("wpb,persist_max", [(1, ALL_LEVELS), (4, ALL_LEVELS), (2, 3), (1, 40)])
+def test_persistent_schedules_bitwise(K, batch, wpb, persist_max):
+    """Levels grouped into persistent launches (all levels in one launch, or runs of small levels
+    between per-level launches) give the per-level result bit for bit; a graph captured from such a
+    factor (which records per-level launches) replays the same result."""
+    print(f"[gpu] persistent schedule wpb={wpb} persist_max={persist_max}", flush=True)
+    import torch
+    xs, ells, ref, b = batch
+    plan, f, xd, ed = run_batch(K, xs, ells)
+    bd = dev(b)
+    base_L = f.export_L()
+    base_x = f.solve(bd).cpu().numpy()
+    f.set_schedule(wpb, persist_max)
+    assert f.schedule() == (wpb, persist_max)
+    f.factorize_batched(xd, 1.5, ed)
+    assert np.array_equal(f.export_L(), base_L)
+    g = f.capture(xd, bd, 1.5, ell_dev=ed)
+    info = g.info()
+    print(f"[gpu] graph {info}", flush=True)
+    assert not info["persistent"] and f.schedule() == (wpb, persist_max)
+    for rep in range(2):
+        out = g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), base_x), f"replay {rep}"
+        f.factorize_batched(xd, 1.5, ed)  # eager work between replays
+        torch.cuda.synchronize()
 
 
 def test_single_problem_graph(K):

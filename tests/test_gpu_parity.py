@@ -101,6 +101,22 @@ def test_index_gap_escapes_do_not_change_the_factor(K, limit, prec):
         assert np.array_equal(f.export_L(), R.L)
 
 
+@pytest.mark.parametrize("persist_max", [2**63 - 1, 16])
+def test_persistent_factorization_bitwise(K, persist_max):
+    """The whole factorization in one persistent launch (or its small levels grouped) equals the
+    oracle bit for bit, update counts included."""
+    print(f"[gpu] persistent factorization persist_max={persist_max}", flush=True)
+    w = W.small_uniform_2d()
+    P, th, R = oracle_factor(w.points, w.rho, "max", w.nu, w.lengthscale)
+    plan = K.analyze(w.points, w.rho)
+    f = K.Factor(plan, "fp64")
+    f.set_schedule(4, persist_max)
+    f.factorize(dev(w.points), w.nu, w.lengthscale, count_updates=True)
+    st = f.stats()
+    assert st.updates == R.updates and st.nonpositive == R.nonpositive
+    assert np.array_equal(f.export_L(), R.L)
+
+
 def test_factor_is_deterministic(K):
     print("[gpu] determinism", flush=True)
     w = W.small_uniform_2d()
