@@ -59,6 +59,37 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_copy_gbs(gib=2):
+    """Device-to-device copy rate (bytes read + written per second) of a plain gib-GiB copy, GB/s:
+    the HBM rate this device delivers to a streaming kernel, reported beside the 8 TB/s spec."""
+    import torch
+    src = torch.ones(gib * 2 ** 30 // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / 5 / 1e3
+    rate = 2 * src.numel() * 8 / t / 1e9
+    del src, dst
+    return rate
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def algorithmic_bytes(prec, nnz, updates):
     """Bytes one factorization must move: per entry a row index read and an L write,
     per Schur update a gathered L value plus its column index (FP64: 12 + 12; MIXED: 8 + 8)."""
@@ -67,7 +98,7 @@ def algorithmic_bytes(prec, nnz, updates):
     return 8 * nnz + 8 * updates
 
 
-def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol):
+def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol, keep_L=False):
     import torch
     import paper_1706_02205_amd as K
     torch.cuda.synchronize()
@@ -116,7 +147,7 @@ def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol):
                   "dense_pairs_per_s": n2 * info.iterations / (info.t_matvec_ms / 1e3)}
     return dict(wall=wall, t_factor=t_fac, t_solve=t_sol, updates=st.updates, rank=st2.rank,
                 nonpositive=st2.nonpositive, shifted=st2.shifted, exp_hard=st2.exp_hard, t_upload=t_upload,
-                workspace_bytes=f.workspace_bytes, refine=refine)
+                workspace_bytes=f.workspace_bytes, refine=refine, L=f.export_L() if keep_L else None)
 
 
 def cpu_baseline(m):
@@ -132,7 +163,7 @@ def cpu_baseline(m):
     O.ichol(P, th)
     t_ichol = time.perf_counter() - t
     return {"value": P.nnz / (t_theta + t_ichol), "unit": "S-entries/s", "cores": O.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"same recipe at N={m * m} ({m}x{m} jittered grid, Matern nu=1/2 l=0.1, rho=4, nnz={P.nnz}); "
                       f"Theta on S {t_theta:.2f} s on {O.num_threads()} threads + ICHOL(0) {t_ichol:.2f} s on 1 thread"}
 
@@ -238,6 +269,34 @@ def run_serving(args):
                   for r in runs]}), flush=True)
 
 
+def sampled_error(plan, points, L, nu, ell, npairs, seed):
+    """Sampled relative Frobenius error E = ||(LL^T - Theta)_pairs|| / ||Theta_pairs|| over npairs index
+    pairs drawn uniformly with replacement (the error measure of Section 4.4), from the exported
+    factor: (LL^T)_ij as sparse row dot products (scipy), Theta_ij from the closed forms (numpy exp).
+    A report of the GPU result, not a parity check."""
+    import scipy.sparse as sp
+    from paper_1706_02205_amd import workloads as W
+    perm, _, colptr, rowidx = plan.export()
+    xh = points[perm]
+    n = len(perm)
+    Lr = sp.csc_matrix((L, rowidx, colptr), shape=(n, n)).tocsr()
+    pairs = W.random_pairs(n, npairs, seed)
+    num = den = 0.0
+    for c in range(0, npairs, 20000):
+        a, b = pairs[c:c + 20000, 0], pairs[c:c + 20000, 1]
+        llt = np.asarray(Lr[a].multiply(Lr[b]).sum(axis=1)).ravel()
+        r = np.sqrt(((xh[a] - xh[b]) ** 2).sum(axis=1)) / ell
+        if nu == 0.5:
+            th = np.exp(-r)
+        elif nu == 1.5:
+            th = (1 + np.sqrt(3) * r) * np.exp(-np.sqrt(3) * r)
+        else:
+            th = (1 + np.sqrt(5) * r + 5 * r * r / 3) * np.exp(-np.sqrt(5) * r)
+        num += float(((llt - th) ** 2).sum())
+        den += float((th ** 2).sum())
+    return float(np.sqrt(num / den))
+
+
 def run_supernodal(args):
     """N = 2e5 points iid uniform in [0,1]^3, Matern-5/2 l=0.2, rho=3: supernodal ordering and block-closed
     pattern, mixed factorization, one solve."""
@@ -255,9 +314,12 @@ def run_supernodal(args):
     prec = args.prec if args.prec != "both" else "mixed"
     # the smooth kernel leaves many nonpositive pivots at rho = 3: the paper's zeroing rule keeps L bounded
     pivot, tau = "zero", 0.0
-    r = run_gpu(w, prec, args.steps, args.warmup, plan, pivot, tau, 0.0)
+    r = run_gpu(w, prec, args.steps, args.warmup, plan, pivot, tau, 0.0, keep_L=True)
     nnz = info["nnz"]
     tf = float(np.mean(r["t_factor"]))
+    t = time.perf_counter()
+    err = sampled_error(plan, w.points, r["L"], w.nu, w.lengthscale, 200_000, 1005)
+    log(f"[bench] sampled error E of the GPU factor (200,000 pairs): {err:.3e} ({time.perf_counter() - t:.1f} s)")
     print(json.dumps({
         "metric": "S-entries factored/s (supernodal pattern, 3-D)", "value": nnz * args.steps / r["wall"],
         "unit": "S-entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -267,6 +329,7 @@ def run_supernodal(args):
                    "levels": info["nlevels"], "prec": prec},
         "factor_only": {"value": nnz / tf, "ms": tf * 1e3}, "solve_ms": float(np.mean(r["t_solve"])) * 1e3,
         "updates": r["updates"], "nonpositive": r["nonpositive"], "rank": r["rank"],
+        "sampled_error_E": err, "sampled_error_pairs": 200_000,
         "host_analysis_s": t_analysis}), flush=True)
 
 
@@ -328,6 +391,8 @@ def main():
         log(f"[bench] copy calibration: 3 x {args.copy_mib} MiB device-to-device")
         del src, dst
 
+    copy_gbs = measured_copy_gbs()
+    log(f"[bench] device-to-device copy: {copy_gbs:.0f} GB/s (read + write)")
     precs = ["fp64", "mixed"] if args.prec == "both" else [args.prec]
     nnz = info["nnz"]
     entries = {}
@@ -347,6 +412,7 @@ def main():
             "dtype": "f64" if prec == "fp64" else "f32-updates/f64-pivots", "pivot": pivot,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                         "measured_copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                          "kernel": "ichol_level (Theta fused), one launch per DAG level",
                          "launches_per_factorization": launches,
                          "algorithmic_bytes_per_launch": B / launches,
