@@ -12,7 +12,8 @@
 struct kc_factor {
     int64_t n = 0, nnz = 0, nnz_rows = 0, nunits = 0;
     int32_t d = 0;
-    int32_t cap = 0;          // LDS entries per wavefront (longest row, rounded up)
+    int32_t cap = 0;          // LDS entries of the staged row (longest row + 2, rounded up)
+    int32_t nbuck = 0;        // bucket directory of the staged row (0: cursor merge)
     int32_t wpb = 4;          // wavefronts per block of the factorization kernel
     int64_t persist_max = 0;  // levels with at most this many units run in persistent launches
     int32_t num_cu = 0;       // compute units of the factor's device
@@ -35,6 +36,11 @@ struct kc_factor {
     double* diag = nullptr;   // MIXED only
     kc::Unit* units = nullptr;
     int64_t* unit_off_dev = nullptr;  // nlevels + 1, units of each level
+    // block units of the factorization for 1, 2 and 4 wavefronts per workgroup:
+    // 64 * wpb consecutive entries of one column each, grouped by level
+    kc::Unit* bunits[3] = {nullptr, nullptr, nullptr};
+    int64_t* boff_dev[3] = {nullptr, nullptr, nullptr};
+    std::vector<int64_t> boff[3];
     int32_t* fwd_rows = nullptr;
     int32_t* bwd_short = nullptr;
     kc::LongCol* bwd_long = nullptr;

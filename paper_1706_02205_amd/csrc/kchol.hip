@@ -182,7 +182,6 @@ __device__ __forceinline__ int xcd_block() {
 // Everything one work unit reads and writes.
 template <typename VT>
 struct IcholArgs {
-    const Unit* units;
     const int64_t* colptr;
     const int32_t* rowidx;
     const uint32_t* csc2csr;
@@ -203,20 +202,53 @@ struct IcholArgs {
     int policy;
     double tau;
     int cap;
+    int nbuck;  // 0: cursor merge; else buckets of the staged row's directory (a power of 2)
+    int count;  // count the Schur updates
     unsigned long long* counters;
 };
 
-// One work unit: 64 consecutive entries of column j, one per lane of the wave.
-// sval/sidx: the wave's own LDS region (cap entries).
-template <int TWONU, bool COUNT, typename VT, bool BATCH>
-__device__ __forceinline__ void factor_unit(const IcholArgs<VT>& a, int64_t u, int lane, VT* sval, int32_t* sidx) {
-    const Unit* __restrict__ units = a.units;
+// Row j's parents (indices and L_ji) into the workgroup's LDS, staged by all its
+// threads once for every wave of the block; returns their number.
+template <typename VT>
+__device__ __forceinline__ int stage_row(const IcholArgs<VT>& a, int j, VT* sval, int32_t* sidx) {
+    const int64_t t0 = a.rowptr[j];
+    const int np = int(a.rowend[j] - 1 - t0);  // row j without its diagonal
+    for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        sidx[t] = a.colidx[t0 + t];
+        sval[t] = a.Lv[t0 + t];
+    }
+    if (threadIdx.x == 0) sidx[np] = INT_MAX;  // sentinel ends every cursor walk
+    return np;
+}
+
+// Bucket directory of the staged row for long rows: bucket b holds the parents i
+// with i >> shift == b, at positions [sb[b], sb[b+1]) of sidx (nb buckets cover
+// [0, j)).  A lookup is then one directory read and a probe or two, independent
+// of the other lookups, instead of a cursor that advances one dependent LDS read
+// at a time.  Built by all threads of the workgroup; returns the shift.
+__device__ __forceinline__ int build_buckets(const int32_t* sidx, int np, int j, int nb, uint16_t* sb) {
+    int shift = 0;
+    while ((j >> shift) >= nb) ++shift;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        const int bq = sidx[q] >> shift, bp = q ? (sidx[q - 1] >> shift) : -1;
+        for (int b = bp + 1; b <= bq; ++b) sb[b] = uint16_t(q);
+    }
+    const int bl = np ? (sidx[np - 1] >> shift) : -1;
+    for (int b = bl + 1 + int(threadIdx.x); b <= nb; b += int(blockDim.x)) sb[b] = uint16_t(np);
+    return shift;
+}
+
+// 64 consecutive entries of column j starting at `first` (first < length of the
+// column), one per lane of the wave; sval/sidx hold row j's np parents (and sb,
+// when BUCKETS, their directory with the given shift).
+template <int TWONU, typename VT, bool BUCKETS>
+__device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, int first, int np, int lane,
+                                               const VT* sval, const int32_t* sidx, const uint16_t* sb,
+                                               int shift) {
     const int64_t* __restrict__ colptr = a.colptr;
     const int32_t* __restrict__ rowidx = a.rowidx;
     const uint32_t* __restrict__ csc2csr = a.csc2csr;
     const int64_t* __restrict__ rowptr = a.rowptr;
-    const int64_t* __restrict__ rowend = a.rowend;
-    const int32_t* __restrict__ colidx = a.colidx;
     const uint32_t* __restrict__ cdelta = a.cdelta;
     const uint32_t* __restrict__ escptr = a.escptr;
     const int32_t* __restrict__ esc = a.esc;
@@ -229,18 +261,6 @@ __device__ __forceinline__ void factor_unit(const IcholArgs<VT>& a, int64_t u, i
     double ell = a.ell;
     unsigned long long* __restrict__ counters = a.counters;
 
-    const int j = __builtin_amdgcn_readfirstlane(units[u].col);
-    const int first = __builtin_amdgcn_readfirstlane(units[u].first);
-    const int64_t t0 = rowptr[j];
-    const int np = int(rowend[j] - 1 - t0);  // parents of j: row j without its diagonal
-    wave_lds_sync();  // the wave's previous unit is done with the staging area
-    for (int t = lane; t < np; t += kWave) {
-        sidx[t] = colidx[t0 + t];
-        sval[t] = Lv[t0 + t];
-    }
-    if (lane == 0) sidx[np] = INT_MAX;  // sentinel ends every cursor walk
-    wave_lds_sync();
-
     double dacc = 1.0;  // Theta_jj
     for (int t = 0; t < np; ++t) {
         double v = double(sval[t]);
@@ -250,7 +270,7 @@ __device__ __forceinline__ void factor_unit(const IcholArgs<VT>& a, int64_t u, i
     const int64_t e = colptr[j] + first + lane;
     const bool active = e < colptr[j + 1];
     const int k = active ? rowidx[e] : j;
-    if constexpr (BATCH) ell = a.ells[a.inst[j]];  // lengthscale of j's instance
+    if (a.ells) ell = a.ells[a.inst[j]];  // a batch: lengthscale of j's instance
     int hard = 0;
     VT acc;
     if constexpr (sizeof(VT) == 8)
@@ -295,12 +315,28 @@ __device__ __forceinline__ void factor_unit(const IcholArgs<VT>& a, int64_t u, i
                                 ++ec;
                             }
                             const int i = cur;
-                            while (sidx[q] < i) ++q;
-                            if (sidx[q] == i) {
-                                const VT lji = sval[q];
+                            int hit;
+                            if constexpr (BUCKETS) {
+                                const int b = i >> shift;
+                                const int q0 = sb[b], qe = sb[b + 1];
+                                const int c0 = sidx[q0], c1 = sidx[q0 + 1];  // q0 + 1 <= np + 1 < cap
+                                hit = (q0 < qe && c0 == i) ? q0 : (q0 + 1 < qe && c1 == i) ? q0 + 1 : -1;
+                                if (hit < 0 && qe - q0 > 2) {  // a crowded bucket: scan the rest
+                                    for (int r = q0 + 2; r < qe; ++r)
+                                        if (sidx[r] == i) {
+                                            hit = r;
+                                            break;
+                                        }
+                                }
+                            } else {
+                                while (sidx[q] < i) ++q;
+                                hit = sidx[q] == i ? q : -1;
+                            }
+                            if (hit >= 0) {
+                                const VT lji = sval[hit];
                                 if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-val[t], lji, acc);
                                 else acc = __builtin_fmaf(-val[t], lji, acc);
-                                if (COUNT && lji != VT(0)) ++hits;
+                                if (a.count && lji != VT(0)) ++hits;
                             }
                         }
                     }
@@ -336,41 +372,75 @@ __device__ __forceinline__ void factor_unit(const IcholArgs<VT>& a, int64_t u, i
         if (zero) atomicAdd(counters + kNonpos, 1ull);
         if (shifted) atomicAdd(counters + kShifted, 1ull);
     }
-    if (COUNT) {
+    if (a.count) {
         const unsigned long long tot = wave_sum(hits);
         if (lane == 0 && tot) atomicAdd(counters + kUpdates, tot);
     }
     if (hard && active) atomicAdd(counters + kExpHard, 1ull);
 }
 
-// One DAG level per launch: a wave per unit.
-template <int TWONU, bool COUNT, typename VT, int WPB, bool BATCH>
-__global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, int64_t ubeg, int64_t uend) {
+// One DAG level per launch.  A workgroup owns a block unit: 64 * WPB consecutive
+// entries of one column, 64 per wave, with the column's row staged once in LDS.
+template <int TWONU, typename VT, int WPB>
+__global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, const Unit* __restrict__ bunits,
+                                                           int64_t ubeg, int64_t uend) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    VT* sval = reinterpret_cast<VT*>(smem) + wave * a.cap;
-    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(WPB) * a.cap * sizeof(VT)) + wave * a.cap;
-    const int64_t u = ubeg + int64_t(xcd_block()) * WPB + wave;
-    if (u < uend) factor_unit<TWONU, COUNT, VT, BATCH>(a, u, lane, sval, sidx);
+    VT* sval = reinterpret_cast<VT*>(smem);
+    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(a.cap) * sizeof(VT));
+    uint16_t* sb = reinterpret_cast<uint16_t*>(smem + size_t(a.cap) * (sizeof(VT) + sizeof(int32_t)));
+    const int64_t bu = ubeg + xcd_block();
+    if (bu >= uend) return;  // the whole workgroup
+    const int j = __builtin_amdgcn_readfirstlane(bunits[bu].col);
+    const int first = __builtin_amdgcn_readfirstlane(bunits[bu].first) + wave * kWave;
+    const int np = stage_row(a, j, sval, sidx);
+    __syncthreads();
+    int shift = 0;
+    if (a.nbuck) {
+        shift = build_buckets(sidx, np, j, a.nbuck, sb);
+        __syncthreads();
+    }
+    if (a.colptr[j] + first < a.colptr[j + 1]) {
+        if (a.nbuck) factor_entries<TWONU, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
+        else factor_entries<TWONU, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+    }
 }
 
-// Levels [l0, l1) in one persistent launch: the waves of a grid that is resident
-// as a whole (cooperative launch) stride over each level's units, and a grid-wide
-// barrier separates consecutive levels.
-template <int TWONU, bool COUNT, typename VT, int WPB, bool BATCH>
-__global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a, const int64_t* __restrict__ unit_off,
-                                                                int l0, int l1) {
+// Levels [l0, l1) in one persistent launch: the workgroups of a grid that is
+// resident as a whole (cooperative launch) stride over each level's block units,
+// and a grid-wide barrier separates consecutive levels.
+template <int TWONU, typename VT, int WPB>
+__global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a, const Unit* __restrict__ bunits,
+                                                                const int64_t* __restrict__ boff, int l0, int l1) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    VT* sval = reinterpret_cast<VT*>(smem) + wave * a.cap;
-    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(WPB) * a.cap * sizeof(VT)) + wave * a.cap;
-    const int64_t slot = int64_t(xcd_block()) * WPB + wave, stride = int64_t(gridDim.x) * WPB;
+    VT* sval = reinterpret_cast<VT*>(smem);
+    int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(a.cap) * sizeof(VT));
+    uint16_t* sb = reinterpret_cast<uint16_t*>(smem + size_t(a.cap) * (sizeof(VT) + sizeof(int32_t)));
+    const int64_t slot = xcd_block(), stride = gridDim.x;
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     for (int l = l0; l < l1; ++l) {
-        const int64_t ub = unit_off[l], ue = unit_off[l + 1];
-        for (int64_t u = ub + slot; u < ue; u += stride) factor_unit<TWONU, COUNT, VT, BATCH>(a, u, lane, sval, sidx);
+        const int64_t ub = boff[l], ue = boff[l + 1];
+        for (int64_t bu = ub + slot; bu < ue; bu += stride) {  // the same trip count for the whole workgroup
+            const int j = __builtin_amdgcn_readfirstlane(bunits[bu].col);
+            const int first = __builtin_amdgcn_readfirstlane(bunits[bu].first) + wave * kWave;
+            const int np = stage_row(a, j, sval, sidx);
+            __syncthreads();
+            int shift = 0;
+            if (a.nbuck) {
+                shift = build_buckets(sidx, np, j, a.nbuck, sb);
+                __syncthreads();
+            }
+            if (a.colptr[j] + first < a.colptr[j + 1]) {
+                if (a.nbuck)
+                    factor_entries<TWONU, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
+                else
+                    factor_entries<TWONU, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+            }
+            __syncthreads();  // the staged row is free again
+        }
         grid.sync();
     }
 }
@@ -692,7 +762,7 @@ BwdSchedule backward_schedule(const kc::Plan& p) {
 
 struct Layout {
     size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, cdelta, escptr, esc, L, Lcsc, diag,
-        units, unit_off, fwd, bshort,
+        units, unit_off, bunits[3], boff[3], fwd, bshort,
         blong, bchunks, inst, total;
 };
 
@@ -723,6 +793,13 @@ Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
     o.diag = take(prec == KC_FP64 ? 0 : n * sizeof(double));
     o.units = take(p.units.size() * sizeof(Unit));
     o.unit_off = take((size_t(p.nlevels) + 1) * sizeof(int64_t));
+    for (int w = 0; w < 3; ++w) {
+        const int per = kWave << w;
+        size_t nb = 0;
+        for (const Unit& u : p.units) nb += (u.first % per == 0);
+        o.bunits[w] = take(nb * sizeof(Unit));
+        o.boff[w] = take((size_t(p.nlevels) + 1) * sizeof(int64_t));
+    }
     o.fwd = take(n * sizeof(int32_t));
     o.bshort = take(b.shortc.size() * sizeof(int32_t));
     o.blong = take(b.longc.size() * sizeof(kc::LongCol));
@@ -742,14 +819,43 @@ int twonu_of(double nu) {
 unsigned grid_for(int64_t items, int per_block) { return unsigned((items + per_block - 1) / per_block); }
 
 // LDS entries per wavefront for staging row j (its parents plus a sentinel).
-int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 1 + 15) / 16 * 16); }
+int wpb_slot(int wpb) { return wpb == 4 ? 2 : wpb == 2 ? 1 : 0; }
+
+// Block units for `wpb` wavefronts per workgroup from the plan's 64-entry units
+// (each column's units are consecutive and start at entry 0).
+void block_units(const kc::Plan& p, int wpb, std::vector<Unit>& bu, std::vector<int64_t>& off) {
+    const int per = kWave * wpb;
+    bu.clear();
+    off.assign(size_t(p.nlevels) + 1, 0);
+    for (int32_t v = 0; v < p.nlevels; ++v) {
+        for (int64_t u = p.unit_off[size_t(v)]; u < p.unit_off[size_t(v) + 1]; ++u)
+            if (p.units[size_t(u)].first % per == 0) bu.push_back(p.units[size_t(u)]);
+        off[size_t(v) + 1] = int64_t(bu.size());
+    }
+}
+
+int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 2 + 15) / 16 * 16); }
+
+// Rows longer than this get a bucket directory (the cursor merge costs one
+// dependent LDS read per step; fine for short rows, slow for long ones).
+constexpr int64_t kBucketRows = 512;
+int32_t bucket_count(const kc::Plan& p) {
+    if (p.max_row <= kBucketRows) return 0;
+    int32_t nb = 1;
+    while (nb < 2 * p.max_row && nb < 8192) nb <<= 1;
+    return nb;
+}
+
+size_t factor_lds(const kc_factor* f, size_t vt) {
+    return (size_t(f->cap) * (vt + sizeof(int32_t)) + (f->nbuck ? size_t(f->nbuck + 1) * sizeof(uint16_t) : 0) + 15) /
+           16 * 16;
+}
 
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 template <typename VT>
 IcholArgs<VT> ichol_args(const kc_factor* f, double ell, const double* ells, int pol, double tau) {
     IcholArgs<VT> a;
-    a.units = f->units;
     a.colptr = f->colptr;
     a.rowidx = f->rowidx;
     a.csc2csr = f->csc2csr;
@@ -770,56 +876,49 @@ IcholArgs<VT> ichol_args(const kc_factor* f, double ell, const double* ells, int
     a.policy = pol;
     a.tau = tau;
     a.cap = f->cap;
+    a.nbuck = f->nbuck;
+    a.count = 0;
     a.counters = f->counters;
     return a;
 }
 
-// One level [ub, ue) as its own launch, or levels [l0, l1) (at most maxu units
-// each) as one cooperative persistent launch.
-template <int TN, bool C, typename VT, int WPB, bool B>
+// One level (block units [ub, ue)) as its own launch, or levels [l0, l1) (at
+// most maxb block units each) as one cooperative persistent launch.
+template <int TN, typename VT, int WPB>
 kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1,
-                     int64_t maxu, bool persistent, hipStream_t s) {
-    const size_t lds = size_t(WPB) * f->cap * (sizeof(VT) + sizeof(int32_t));
+                     int64_t maxb, bool persistent, hipStream_t s) {
+    const size_t lds = factor_lds(f, sizeof(VT));
+    const int w = wpb_slot(WPB);
     if (!persistent) {
-        ichol_level<TN, C, VT, WPB, B><<<grid_for(ue - ub, WPB), WPB * kWave, lds, s>>>(a, ub, ue);
+        if (ue <= ub) return KC_OK;
+        ichol_level<TN, VT, WPB><<<unsigned(ue - ub), WPB * kWave, lds, s>>>(a, f->bunits[w], ub, ue);
         KC_LAUNCH_CHECK();
         return KC_OK;
     }
-    const void* fn = reinterpret_cast<const void*>(&ichol_persistent<TN, C, VT, WPB, B>);
+    const void* fn = reinterpret_cast<const void*>(&ichol_persistent<TN, VT, WPB>);
     int per_cu = 0;
     KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WPB * kWave, lds));
     if (per_cu < 1) {
         kc::set_error("kc_factorize: the persistent kernel does not fit on a compute unit");
         return KC_EHIP;
     }
-    // every block resident at once (the cooperative launch refuses anything larger)
-    const int64_t want = std::max<int64_t>(1, int64_t(grid_for(maxu, WPB)));
-    const unsigned blocks = unsigned(std::min<int64_t>(int64_t(per_cu) * f->num_cu, want));
+    // every workgroup resident at once (the cooperative launch refuses anything larger)
+    const unsigned blocks = unsigned(std::min<int64_t>(int64_t(per_cu) * f->num_cu, std::max<int64_t>(1, maxb)));
     IcholArgs<VT> av = a;
-    const int64_t* uo = f->unit_off_dev;
+    const Unit* bu = f->bunits[w];
+    const int64_t* bo = f->boff_dev[w];
     int l0v = l0, l1v = l1;
-    void* args[] = {&av, &uo, &l0v, &l1v};
+    void* args[] = {&av, &bu, &bo, &l0v, &l1v};
     KC_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(WPB * kWave), args, unsigned(lds), s));
     return KC_OK;
 }
 
-template <int TN, bool C, typename VT, bool B>
+template <int TN, typename VT>
 kc_status launch_wpb(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1, int64_t maxu,
                      bool persistent, hipStream_t s) {
-    if (f->wpb == 4) return launch_one<TN, C, VT, 4, B>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-    if (f->wpb == 2) return launch_one<TN, C, VT, 2, B>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-    return launch_one<TN, C, VT, 1, B>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-}
-
-template <int TN, typename VT>
-kc_status launch_tn(const kc_factor* f, bool cnt, bool batch, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0,
-                    int l1, int64_t maxu, bool persistent, hipStream_t s) {
-    if (cnt) {
-        return batch ? launch_wpb<TN, true, VT, true>(f, a, ub, ue, l0, l1, maxu, persistent, s)
-                     : launch_wpb<TN, true, VT, false>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-    }
-    return batch ? launch_wpb<TN, false, VT, true>(f, a, ub, ue, l0, l1, maxu, persistent, s)
-                 : launch_wpb<TN, false, VT, false>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    if (f->wpb == 4) return launch_one<TN, VT, 4>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    if (f->wpb == 2) return launch_one<TN, VT, 2>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    return launch_one<TN, VT, 1>(f, a, ub, ue, l0, l1, maxu, persistent, s);
 }
 
 // The levels of the factorization: a level with more than f->persist_max units is
@@ -827,30 +926,31 @@ kc_status launch_tn(const kc_factor* f, bool cnt, bool batch, const IcholArgs<VT
 template <typename VT>
 kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const double* ells, int pol, double tau,
                         hipStream_t s) {
-    const IcholArgs<VT> a = ichol_args<VT>(f, ell, ells, pol, tau);
-    const bool batch = ells != nullptr;
+    IcholArgs<VT> a = ichol_args<VT>(f, ell, ells, pol, tau);
+    a.count = cnt ? 1 : 0;
     auto go = [&](int64_t ub, int64_t ue, int l0, int l1, int64_t maxu, bool persistent) {
-        if (tn == 1) return launch_tn<1, VT>(f, cnt, batch, a, ub, ue, l0, l1, maxu, persistent, s);
-        if (tn == 3) return launch_tn<3, VT>(f, cnt, batch, a, ub, ue, l0, l1, maxu, persistent, s);
-        return launch_tn<5, VT>(f, cnt, batch, a, ub, ue, l0, l1, maxu, persistent, s);
+        if (tn == 1) return launch_wpb<1, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        if (tn == 3) return launch_wpb<3, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        return launch_wpb<5, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
     };
     const int nl = int(f->unit_off.size()) - 1;
+    const std::vector<int64_t>& bo = f->boff[wpb_slot(f->wpb)];
     int v = 0;
     while (v < nl) {
-        const int64_t cnt_v = f->unit_off[v + 1] - f->unit_off[v];
+        const int64_t cnt_v = f->unit_off[v + 1] - f->unit_off[v];  // 64-entry units: the grouping criterion
         if (cnt_v > f->persist_max) {
-            const kc_status st = go(f->unit_off[v], f->unit_off[v + 1], v, v + 1, cnt_v, false);
+            const kc_status st = go(bo[v], bo[v + 1], v, v + 1, bo[v + 1] - bo[v], false);
             if (st != KC_OK) return st;
             ++v;
             continue;
         }
         int w = v;
-        int64_t maxu = 0;
+        int64_t maxb = 0;
         while (w < nl && f->unit_off[w + 1] - f->unit_off[w] <= f->persist_max) {
-            maxu = std::max<int64_t>(maxu, f->unit_off[w + 1] - f->unit_off[w]);
+            maxb = std::max<int64_t>(maxb, bo[w + 1] - bo[w]);
             ++w;
         }
-        const kc_status st = maxu > 0 ? go(0, 0, v, w, maxu, true) : KC_OK;  // a run of empty levels needs nothing
+        const kc_status st = maxb > 0 ? go(0, 0, v, w, maxb, true) : KC_OK;  // a run of empty levels needs nothing
         if (st != KC_OK) return st;
         v = w;
     }
@@ -1188,9 +1288,13 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     if (!f) return KC_ENOMEM;
     const size_t vt = prec == KC_FP64 ? sizeof(double) : sizeof(float);
     f->cap = lds_cap(p);
-    if (size_t(4) * f->cap * (vt + 4) <= 64 * 1024) f->wpb = 4;
-    else if (size_t(f->cap) * (vt + 4) <= kMaxLdsBytes) f->wpb = 1;
-    else {
+    f->nbuck = bucket_count(p);
+    if (factor_lds(f.get(), vt) <= kMaxLdsBytes) {
+        // a workgroup covers 64 * wpb entries of one column: more wavefronts share one
+        // staged row on long columns, fewer leave less padding on short ones
+        const double avg = double(p.nnz()) / double(std::max<int64_t>(1, p.n));
+        f->wpb = avg >= 1024.0 ? 4 : avg >= 512.0 ? 2 : 1;
+    } else {
         kc::set_error("kc_factor_create: a row of S is too long to stage in LDS (" + std::to_string(p.max_row) +
                       " entries)");
         return KC_ERANGE;
@@ -1224,6 +1328,10 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->diag = prec == KC_MIXED ? reinterpret_cast<double*>(base + o.diag) : nullptr;
     f->units = reinterpret_cast<Unit*>(base + o.units);
     f->unit_off_dev = reinterpret_cast<int64_t*>(base + o.unit_off);
+    for (int w = 0; w < 3; ++w) {
+        f->bunits[w] = reinterpret_cast<Unit*>(base + o.bunits[w]);
+        f->boff_dev[w] = reinterpret_cast<int64_t*>(base + o.boff[w]);
+    }
     f->fwd_rows = reinterpret_cast<int32_t*>(base + o.fwd);
     f->bwd_short = reinterpret_cast<int32_t*>(base + o.bshort);
     f->bwd_long = reinterpret_cast<kc::LongCol*>(base + o.blong);
@@ -1253,6 +1361,15 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     KC_HIP(hipMemcpyAsync(f->units, p.units.data(), p.units.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->unit_off_dev, p.unit_off.data(), p.unit_off.size() * sizeof(int64_t),
                           hipMemcpyHostToDevice, s));
+    for (int w = 0; w < 3; ++w) {
+        std::vector<Unit> bu;
+        block_units(p, 1 << w, bu, f->boff[w]);
+        if (!bu.empty())
+            KC_HIP(hipMemcpyAsync(f->bunits[w], bu.data(), bu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
+        KC_HIP(hipMemcpyAsync(f->boff_dev[w], f->boff[w].data(), f->boff[w].size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+        KC_HIP(hipStreamSynchronize(s));  // bu is a local buffer
+    }
     KC_HIP(hipMemcpyAsync(f->fwd_rows, p.fwd_rows.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!bs.shortc.empty())
         KC_HIP(hipMemcpyAsync(f->bwd_short, bs.shortc.data(), bs.shortc.size() * sizeof(int32_t),
@@ -1427,7 +1544,7 @@ kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double el
     // level grouping: levels with at most `pm` units share persistent launches
     const int64_t kGroupings[] = {0, 256, 4096, INT64_MAX};
     for (int wpb : {1, 2, 4}) {
-        if (size_t(wpb) * f->cap * (vt + 4) > 64 * 1024) continue;
+        if (factor_lds(f, vt) > kMaxLdsBytes) continue;
         for (int64_t pm : kGroupings) {
             f->wpb = wpb;
             f->persist_max = pm;
@@ -1467,8 +1584,8 @@ kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max)
         return KC_EINVAL;
     }
     const size_t vt = f->prec == KC_FP64 ? sizeof(double) : sizeof(float);
-    if (size_t(wpb) * f->cap * (vt + 4) > 64 * 1024) {
-        kc::set_error("kc_factor_set_schedule: the staged rows of that many wavefronts do not fit in LDS");
+    if (factor_lds(f, vt) > kMaxLdsBytes) {
+        kc::set_error("kc_factor_set_schedule: the staged row does not fit in LDS");
         return KC_EINVAL;
     }
     f->wpb = wpb;

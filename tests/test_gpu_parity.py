@@ -48,6 +48,9 @@ CASES = [
     ("sphere20d-n1000-matern32-rho3", lambda: W.embedded_sincos(1000, 25), 3.0, "max", 1.5, 0.2, "zero", 0.0),
     ("duplicates-n330", lambda: np.concatenate([W.uniform_points(300, 2, 26), W.uniform_points(300, 2, 26)[:30]]),
      2.0, "max", 0.5, 0.2, "zero", 0.0),
+    # rows longer than 512 entries: the staged row gets a bucket directory instead of the cursor merge
+    ("uniform3d-n6000-matern32-rho4.5-longrows", lambda: W.uniform_points(6000, 3, 31), 4.5, "max", 1.5, 0.2, "zero", 0.0),
+    ("uniform2d-n4000-matern12-rho14-longrows", lambda: W.uniform_points(4000, 2, 31), 14.0, "max", 0.5, 0.2, "zero", 0.0),
 ]
 
 
