@@ -203,7 +203,6 @@ struct IcholArgs {
     double tau;
     int cap;
     int nbuck;  // 0: cursor merge; else buckets of the staged row's directory (a power of 2)
-    int count;  // count the Schur updates
     unsigned long long* counters;
 };
 
@@ -241,7 +240,7 @@ __device__ __forceinline__ int build_buckets(const int32_t* sidx, int np, int j,
 // 64 consecutive entries of column j starting at `first` (first < length of the
 // column), one per lane of the wave; sval/sidx hold row j's np parents (and sb,
 // when BUCKETS, their directory with the given shift).
-template <int TWONU, typename VT, bool BUCKETS>
+template <int TWONU, bool COUNT, typename VT, bool BUCKETS>
 __device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, int first, int np, int lane,
                                                const VT* sval, const int32_t* sidx, const uint16_t* sb,
                                                int shift) {
@@ -336,7 +335,7 @@ __device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, in
                                 const VT lji = sval[hit];
                                 if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-val[t], lji, acc);
                                 else acc = __builtin_fmaf(-val[t], lji, acc);
-                                if (a.count && lji != VT(0)) ++hits;
+                                if (COUNT && lji != VT(0)) ++hits;
                             }
                         }
                     }
@@ -372,7 +371,7 @@ __device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, in
         if (zero) atomicAdd(counters + kNonpos, 1ull);
         if (shifted) atomicAdd(counters + kShifted, 1ull);
     }
-    if (a.count) {
+    if (COUNT) {
         const unsigned long long tot = wave_sum(hits);
         if (lane == 0 && tot) atomicAdd(counters + kUpdates, tot);
     }
@@ -381,7 +380,7 @@ __device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, in
 
 // One DAG level per launch.  A workgroup owns a block unit: 64 * WPB consecutive
 // entries of one column, 64 per wave, with the column's row staged once in LDS.
-template <int TWONU, typename VT, int WPB>
+template <int TWONU, bool COUNT, typename VT, int WPB>
 __global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, const Unit* __restrict__ bunits,
                                                            int64_t ubeg, int64_t uend) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -402,15 +401,15 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, cons
         __syncthreads();
     }
     if (a.colptr[j] + first < a.colptr[j + 1]) {
-        if (a.nbuck) factor_entries<TWONU, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
-        else factor_entries<TWONU, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+        if (a.nbuck) factor_entries<TWONU, COUNT, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
+        else factor_entries<TWONU, COUNT, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
     }
 }
 
 // Levels [l0, l1) in one persistent launch: the workgroups of a grid that is
 // resident as a whole (cooperative launch) stride over each level's block units,
 // and a grid-wide barrier separates consecutive levels.
-template <int TWONU, typename VT, int WPB>
+template <int TWONU, bool COUNT, typename VT, int WPB>
 __global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a, const Unit* __restrict__ bunits,
                                                                 const int64_t* __restrict__ boff, int l0, int l1) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -435,9 +434,9 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a,
             }
             if (a.colptr[j] + first < a.colptr[j + 1]) {
                 if (a.nbuck)
-                    factor_entries<TWONU, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
+                    factor_entries<TWONU, COUNT, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
                 else
-                    factor_entries<TWONU, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+                    factor_entries<TWONU, COUNT, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
             }
             __syncthreads();  // the staged row is free again
         }
@@ -877,25 +876,24 @@ IcholArgs<VT> ichol_args(const kc_factor* f, double ell, const double* ells, int
     a.tau = tau;
     a.cap = f->cap;
     a.nbuck = f->nbuck;
-    a.count = 0;
     a.counters = f->counters;
     return a;
 }
 
 // One level (block units [ub, ue)) as its own launch, or levels [l0, l1) (at
 // most maxb block units each) as one cooperative persistent launch.
-template <int TN, typename VT, int WPB>
+template <int TN, bool C, typename VT, int WPB>
 kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1,
                      int64_t maxb, bool persistent, hipStream_t s) {
     const size_t lds = factor_lds(f, sizeof(VT));
     const int w = wpb_slot(WPB);
     if (!persistent) {
         if (ue <= ub) return KC_OK;
-        ichol_level<TN, VT, WPB><<<unsigned(ue - ub), WPB * kWave, lds, s>>>(a, f->bunits[w], ub, ue);
+        ichol_level<TN, C, VT, WPB><<<unsigned(ue - ub), WPB * kWave, lds, s>>>(a, f->bunits[w], ub, ue);
         KC_LAUNCH_CHECK();
         return KC_OK;
     }
-    const void* fn = reinterpret_cast<const void*>(&ichol_persistent<TN, VT, WPB>);
+    const void* fn = reinterpret_cast<const void*>(&ichol_persistent<TN, C, VT, WPB>);
     int per_cu = 0;
     KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WPB * kWave, lds));
     if (per_cu < 1) {
@@ -913,12 +911,12 @@ kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int
     return KC_OK;
 }
 
-template <int TN, typename VT>
+template <int TN, bool C, typename VT>
 kc_status launch_wpb(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1, int64_t maxu,
                      bool persistent, hipStream_t s) {
-    if (f->wpb == 4) return launch_one<TN, VT, 4>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-    if (f->wpb == 2) return launch_one<TN, VT, 2>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-    return launch_one<TN, VT, 1>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    if (f->wpb == 4) return launch_one<TN, C, VT, 4>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    if (f->wpb == 2) return launch_one<TN, C, VT, 2>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    return launch_one<TN, C, VT, 1>(f, a, ub, ue, l0, l1, maxu, persistent, s);
 }
 
 // The levels of the factorization: a level with more than f->persist_max units is
@@ -926,12 +924,16 @@ kc_status launch_wpb(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int
 template <typename VT>
 kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const double* ells, int pol, double tau,
                         hipStream_t s) {
-    IcholArgs<VT> a = ichol_args<VT>(f, ell, ells, pol, tau);
-    a.count = cnt ? 1 : 0;
+    const IcholArgs<VT> a = ichol_args<VT>(f, ell, ells, pol, tau);
     auto go = [&](int64_t ub, int64_t ue, int l0, int l1, int64_t maxu, bool persistent) {
-        if (tn == 1) return launch_wpb<1, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-        if (tn == 3) return launch_wpb<3, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-        return launch_wpb<5, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        if (cnt) {
+            if (tn == 1) return launch_wpb<1, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+            if (tn == 3) return launch_wpb<3, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+            return launch_wpb<5, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        }
+        if (tn == 1) return launch_wpb<1, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        if (tn == 3) return launch_wpb<3, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        return launch_wpb<5, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
     };
     const int nl = int(f->unit_off.size()) - 1;
     const std::vector<int64_t>& bo = f->boff[wpb_slot(f->wpb)];
