@@ -333,6 +333,34 @@ def run_supernodal(args):
         "host_analysis_s": t_analysis}), flush=True)
 
 
+def run_dense(args):
+    """The dense Theta product alone (conjugate gradients' matrix product): Y = Theta X on the 10^6-point
+    grid with 8 right-hand sides, Theta generated on the fly (10^12 kernel evaluations per product)."""
+    import torch
+    import paper_1706_02205_amd as K
+    from paper_1706_02205_amd import workloads as W
+    w = W.large_grid_2d()
+    x = torch.from_numpy(w.points).cuda()
+    X = torch.from_numpy(w.rhs()).cuda()
+    for _ in range(args.warmup):
+        K.dense_matvec(x, X, w.nu, w.lengthscale)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        K.dense_matvec(x, X, w.nu, w.lengthscale)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / 1e3 / args.steps
+    pairs = float(w.n) ** 2
+    print(json.dumps({
+        "metric": "kernel evaluations/s in the dense Theta product", "value": pairs / t, "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"dense-{w.name}", "n": w.n, "nrhs": w.nrhs, "kernel": f"matern nu={w.nu} l={w.lengthscale}"}}),
+        flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,9 +375,9 @@ def main():
                     help="also time CG on the dense Theta to this residual with each factor (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
-    ap.add_argument("--workload", default="grid", choices=["grid", "batched", "serve", "supernodal3d"],
+    ap.add_argument("--workload", default="grid", choices=["grid", "batched", "serve", "supernodal3d", "dense"],
                     help="grid: the 10^6-point benchmark (default); batched: 512 independent instances; "
-                         "serve: Poisson trace of factor+solve requests")
+                         "serve: Poisson trace of factor+solve requests; dense: the dense Theta product alone")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--analysis-threads", type=int, default=12)
     ap.add_argument("--instances", type=int, default=512)
@@ -367,6 +395,9 @@ def main():
         return
     if args.workload == "supernodal3d":
         run_supernodal(args)
+        return
+    if args.workload == "dense":
+        run_dense(args)
         return
 
     import paper_1706_02205_amd as K
