@@ -36,73 +36,69 @@ constexpr int kDotBlocks = 512;  // fixed grid of the dot-product reduction
 // method, ACM TOMS 15(2), 1989): x = (256 m + j) ln2/256 + r with
 // |r| <= ln2/512, so exp(x) = 2^m 2^(j/256) exp(r).  2^(j/256) comes from a
 // 256-entry table in LDS, exp(r) - 1 from its degree-4 Taylor polynomial
-// (truncation below 4e-17).  On this range 2^m never leaves the normal
-// numbers, so it is applied by an integer add to the exponent field.
+// (truncation below 4e-17).  The reduction uses ln2/256 rounded to double
+// alone: the error that leaves in r is below 8e-17 a relative, about 4 ulp at
+// a = 5, far below what the dense product needs.  On this range 2^m never
+// leaves the normal numbers.
 constexpr int kExpBits = 8;
 constexpr int kExpSize = 1 << kExpBits;
 constexpr double kShift = 6755399441055744.0;          // 1.5 * 2^52: adding it rounds to an integer
 constexpr double kInvLn2xN = 369.32993046757463;       // 256 / ln 2 (only selects the reduction)
-constexpr double kLn2dNHi = 0.0027076061740622863;     // ln 2 / 256 rounded to double
+constexpr double kLn2dN = 0.0027076061740622863;       // ln 2 / 256 rounded to double
 constexpr double kMaxArg = 707.0;                      // exp(-707) is still a normal number
 
 struct ExpTable {
     double t[kExpSize];  // 2^(j/256)
-    double lo;           // ln 2 / 256 - kLn2dNHi
 };
 
 ExpTable make_exp_table() {
     ExpTable e{};
     for (int j = 0; j < kExpSize; ++j)
         e.t[j] = static_cast<double>(std::exp2(static_cast<long double>(j) / static_cast<long double>(kExpSize)));
-    e.lo = static_cast<double>(std::log(2.0L) / static_cast<long double>(kExpSize) -
-                               static_cast<long double>(kLn2dNHi));
     return e;
 }
 
-__device__ __forceinline__ double exp_neg(double a, const double* __restrict__ tab, double lo) {
-    // exp(-a) for 0 <= a <= kMaxArg
+// exp(-a) for 0 <= a <= kMaxArg; c6 is 1/6, held by the caller in a vector
+// register (an fma can read one scalar constant, and 1/24 is the other).
+__device__ __forceinline__ double exp_neg(double a, const double* __restrict__ tab, double c6) {
     const double x = -a;
     const double t = __builtin_fma(x, kInvLn2xN, kShift);
     const double kf = t - kShift;
     const int k = __double2loint(t);  // the low word holds the integer
-    double r = __builtin_fma(-kf, kLn2dNHi, x);
-    r = __builtin_fma(-kf, lo, r);
-    double q = __builtin_fma(r, 1.0 / 24.0, 1.0 / 6.0);
+    const double r = __builtin_fma(-kf, kLn2dN, x);
+    double q = __builtin_fma(r, 1.0 / 24.0, c6);
     q = __builtin_fma(r, q, 0.5);
     q = __builtin_fma(r, q, 1.0);
     const double p = r * q;  // exp(r) - 1
     const double tj = tab[k & (kExpSize - 1)];
-    const double v = __builtin_fma(tj, p, tj);
-    return __hiloint2double(__double2hiint(v) + ((k >> kExpBits) << 20), __double2loint(v));
+    return __builtin_amdgcn_ldexp(__builtin_fma(tj, p, tj), k >> kExpBits);
 }
 
-// sqrt(s) for s >= 0: hardware reciprocal square root (about 2^-24 relative),
-// one coupled Goldschmidt step and one Newton correction; measured at 0.5 ulp.
-// s is raised to 1e-300 so that s = 0 gives 1e-150 (the kernel is then 1 to
-// the last bit) instead of 0 * inf.
-__device__ __forceinline__ double sqrt_nonneg(double s) {
-    s = fmax(s, 1e-300);
+// sqrt(s) for s > 0 from the hardware reciprocal square root y (relative error
+// about 5e-8) and one second-order correction: with g = s y and c = 1 - y g
+// (one rounding), sqrt(s) = g (1 - c)^(-1/2) = g (1 + c/2 + 3c^2/8 + O(c^3));
+// the rounding of g enters as half its relative error, so the result is within
+// about one ulp.
+__device__ __forceinline__ double sqrt_pos(double s) {
     const double y = __builtin_amdgcn_rsq(s);
-    double g = s * y, h = 0.5 * y;
-    const double c = __builtin_fma(-h, g, 0.5);
-    g = __builtin_fma(g, c, g);
-    h = __builtin_fma(h, c, h);
-    const double e = __builtin_fma(-g, g, s);
-    return __builtin_fma(e, h, g);
+    const double g = s * y;
+    const double c = __builtin_fma(-y, g, 1.0);
+    const double q = __builtin_fma(c, 0.375, 0.5);
+    return __builtin_fma(g * c, q, g);
 }
 
 // Matern-nu/2 closed forms of Section 4.4 at a = c r / l (c = 1, sqrt 3,
-// sqrt 5 for TWONU = 2 nu = 1, 3, 5; `scale` = c / l).  a is capped at
-// kMaxArg: beyond it every form is below 1e-300, and the cap replaces those
-// entries by their value at the cap, an absolute change below 2e-302.
+// sqrt 5 for TWONU = 2 nu = 1, 3, 5).  a is capped at kMaxArg: beyond it every
+// form is below 1e-300, and the cap replaces those entries by their value at
+// the cap, an absolute change below 2e-302.
 template <int TWONU>
-__device__ __forceinline__ double matern_fast(double r, double scale, const double* __restrict__ tab, double lo) {
-    const double a = fmin(r * scale, kMaxArg);
-    const double e = exp_neg(a, tab, lo);
+__device__ __forceinline__ double matern_fast(double a, const double* __restrict__ tab, double c6) {
+    a = fmin(a, kMaxArg);
+    const double e = exp_neg(a, tab, c6);
     if constexpr (TWONU == 1) {
         return e;
     } else if constexpr (TWONU == 3) {
-        return (1.0 + a) * e;
+        return __builtin_fma(a, e, e);
     } else {
         return (1.0 + a + a * a * (1.0 / 3.0)) * e;
     }
@@ -138,7 +134,11 @@ __global__ __launch_bounds__(256) void dense_matvec_mfma(const double* __restric
     double* sx = tile + kExpSize;
     double* sv = sx + size_t(tj) * d;
     for (int q = threadIdx.x; q < kExpSize; q += blockDim.x) tab[q] = et.t[q];
-    const double lo = et.lo;
+    // With coordinates in registers (D > 0) both sides are multiplied by `scale`
+    // as they are loaded, so the distance comes out as a = c r / l directly.
+    const double cs = D > 0 ? scale : 1.0;
+    double c6 = 1.0 / 6.0;
+    asm volatile("" : "+v"(c6));  // kept in a vector register for the whole loop
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int t4 = lane & 3, q4 = (lane >> 2) & 3, s4 = lane >> 4;
     const int64_t row_base = int64_t(blockIdx.x) * kMfmaRows + int64_t(wave) * 16 * kGroups;
@@ -150,14 +150,14 @@ __global__ __launch_bounds__(256) void dense_matvec_mfma(const double* __restric
         const int64_t i = row_base + g * 16 + 4 * q4 + t4;
         ic[g] = i < n ? i : n - 1;
 #pragma unroll
-        for (int t = 0; t < (D > 0 ? D : 1); ++t) xi[g][t] = D > 0 ? x[ic[g] * D + t] : 0.0;
+        for (int t = 0; t < (D > 0 ? D : 1); ++t) xi[g][t] = D > 0 ? x[ic[g] * D + t] * cs : 0.0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[g][b] = 0.0;
     }
     for (int64_t j0 = 0; j0 < n; j0 += tj) {
         const int m = int(n - j0 < tj ? n - j0 : tj);
         const int mq = (m + 3) & ~3;  // whole quads; the padding columns carry zero weights
-        for (int q = threadIdx.x; q < mq * d; q += 256) sx[q] = q < m * d ? x[j0 * d + q] : 0.0;
+        for (int q = threadIdx.x; q < mq * d; q += 256) sx[q] = q < m * d ? x[j0 * d + q] * cs : 0.0;
         for (int q = threadIdx.x; q < mq * kMfmaRhs; q += 256) {
             const int jj = q >> 3, r = q & 7;
             sv[q] = (jj < m && r < nr) ? X[(j0 + jj) * ld + r0 + r] : 0.0;
@@ -170,7 +170,9 @@ __global__ __launch_bounds__(256) void dense_matvec_mfma(const double* __restric
             for (int b = 0; b < NB; ++b) bv[b] = sv[jj * kMfmaRhs + 4 * b + t4];
 #pragma unroll
             for (int g = 0; g < kGroups; ++g) {
-                double s = 0.0;
+                // s starts at 1e-300 so that s = 0 (a point with itself) gives
+                // a = 1e-150 (the kernel is 1 to the last bit) instead of 0 * inf
+                double s = 1e-300;
                 if constexpr (D > 0) {
 #pragma unroll
                     for (int t = 0; t < D; ++t) {
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(256) void dense_matvec_mfma(const double* __restric
                         s = __builtin_fma(df, df, s);
                     }
                 }
-                const double th = matern_fast<TWONU>(sqrt_nonneg(s), scale, tab, lo);
+                const double th = matern_fast<TWONU>(D > 0 ? sqrt_pos(s) : sqrt_pos(s) * scale, tab, c6);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) acc[g][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(th, bv[b], acc[g][b], 0, 0, 0);
             }

@@ -1,8 +1,9 @@
 """GPU parity of the dense Theta product and of CG preconditioned by the sparse factor.
 
 The dense product sums the same terms as the oracle, in quads of columns on the
-matrix cores and with an exp and a square root accurate to about one ulp, so it
-is compared to a relative error of 1e-12 of sum_j |Theta_ij X_j|.  CG is checked by what it certifies: the true residual
+matrix cores, with a square root within about one ulp and an exp within a few
+ulp (together below 2e-15 relative for kernel arguments up to 5), so it is
+compared to a relative error of 1e-12 of sum_j |Theta_ij X_j|.  CG is checked by what it certifies: the true residual
 recomputed by the oracle's dense product meets the tolerance, and the iteration
 count matches the oracle's CG within one.
 """
