@@ -148,8 +148,9 @@ __device__ __forceinline__ void load_vals(const float* __restrict__ Lv, int64_t 
 
 // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
 // Renumber them so that each XCD receives one contiguous range of blocks: the
-// units of a level are laid out in spatial order, so each XCD's L2 then serves
-// one region of the point cloud.
+// rows and columns of a solve level are laid out in spatial order, so each
+// XCD's L2 then serves one region of the point cloud.  (The factorization's
+// units are ordered by length instead, and keep the plain block order.)
 constexpr int kNumXcd = 8;
 __device__ __forceinline__ int xcd_block() {
     const int b = blockIdx.x, nb = gridDim.x;
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, cons
     VT* sval = reinterpret_cast<VT*>(smem);
     int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(a.cap) * sizeof(VT));
     uint16_t* sb = reinterpret_cast<uint16_t*>(smem + size_t(a.cap) * (sizeof(VT) + sizeof(int32_t)));
-    const int64_t bu = ubeg + xcd_block();
+    const int64_t bu = ubeg + int64_t(blockIdx.x);  // longest first (see block_units)
     if (bu >= uend) return;  // the whole workgroup
     const int j = __builtin_amdgcn_readfirstlane(bunits[bu].col);
     const int first = __builtin_amdgcn_readfirstlane(bunits[bu].first) + wave * kWave;
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a,
     VT* sval = reinterpret_cast<VT*>(smem);
     int32_t* sidx = reinterpret_cast<int32_t*>(smem + size_t(a.cap) * sizeof(VT));
     uint16_t* sb = reinterpret_cast<uint16_t*>(smem + size_t(a.cap) * (sizeof(VT) + sizeof(int32_t)));
-    const int64_t slot = xcd_block(), stride = gridDim.x;
+    const int64_t slot = blockIdx.x, stride = gridDim.x;
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     for (int l = l0; l < l1; ++l) {
         const int64_t ub = boff[l], ue = boff[l + 1];
@@ -822,6 +823,12 @@ int wpb_slot(int wpb) { return wpb == 4 ? 2 : wpb == 2 ? 1 : 0; }
 
 // Block units for `wpb` wavefronts per workgroup from the plan's 64-entry units
 // (each column's units are consecutive and start at entry 0).
+// Block units of each level, longest first.  A workgroup lasts as long as its
+// longest lane, whose walk is the prefix of row k before (k,j); workgroups of a
+// launch start in index order, so putting the longest first shortens the tail in
+// which a level's last workgroups leave most of the chip idle (on the 10^6-point
+// grid, 146.9 -> 138.7 ms in FP64).  The order of independent units does not
+// change any result.
 void block_units(const kc::Plan& p, int wpb, std::vector<Unit>& bu, std::vector<int64_t>& off) {
     const int per = kWave * wpb;
     bu.clear();
@@ -831,6 +838,30 @@ void block_units(const kc::Plan& p, int wpb, std::vector<Unit>& bu, std::vector<
             if (p.units[size_t(u)].first % per == 0) bu.push_back(p.units[size_t(u)]);
         off[size_t(v) + 1] = int64_t(bu.size());
     }
+    const int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    std::atomic<int32_t> next{0};
+    auto work = [&]() {
+        std::vector<std::pair<int64_t, Unit>> tmp;
+        for (int32_t v; (v = next.fetch_add(1)) < p.nlevels;) {
+            const int64_t b0 = off[size_t(v)], b1 = off[size_t(v) + 1];
+            tmp.clear();
+            for (int64_t t = b0; t < b1; ++t) {
+                const Unit un = bu[size_t(t)];
+                const int64_t e0 = p.colptr[size_t(un.col)] + un.first;
+                const int64_t e1 = std::min<int64_t>(e0 + per, p.colptr[size_t(un.col) + 1]);
+                int64_t w = 0;
+                for (int64_t e = e0; e < e1; ++e)
+                    w = std::max<int64_t>(w, int64_t(p.csc2csr[size_t(e)]) - p.rowptr[size_t(p.rowidx[size_t(e)])]);
+                tmp.push_back({w, un});
+            }
+            std::stable_sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+            for (int64_t t = b0; t < b1; ++t) bu[size_t(t)] = tmp[size_t(t - b0)].second;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
 }
 
 int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 2 + 15) / 16 * 16); }
