@@ -147,7 +147,8 @@ def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol, keep_L=False):
                   "dense_pairs_per_s": n2 * info.iterations / (info.t_matvec_ms / 1e3)}
     return dict(wall=wall, t_factor=t_fac, t_solve=t_sol, updates=st.updates, rank=st2.rank,
                 nonpositive=st2.nonpositive, shifted=st2.shifted, exp_hard=st2.exp_hard, t_upload=t_upload,
-                workspace_bytes=f.workspace_bytes, refine=refine, L=f.export_L() if keep_L else None)
+                workspace_bytes=f.workspace_bytes, refine=refine, L=f.export_L() if keep_L else None,
+                schedule=dict(zip(("waves_per_block", "persist_max", "unit_order"), f.schedule())))
 
 
 def cpu_baseline(m):
@@ -190,8 +191,9 @@ def run_batched(args):
     f.factorize_batched(xd, 1.5, ed, pivot, tau, count_updates=True)
     st = f.stats()
     wpb = f.tune(xd, 1.5, ell_dev=ed, pivot=pivot, tau=tau, reps=2)
-    wpb, pm = f.schedule()
-    log(f"[bench] tuner: {wpb} wavefronts per workgroup, levels with <= {pm} units in persistent launches")
+    wpb, pm, order = f.schedule()
+    log(f"[bench] tuner: {wpb} wavefronts per workgroup, levels with <= {pm} units in persistent launches, "
+        f"unit order {order}")
 
     def timed(step):
         for _ in range(args.warmup):
@@ -219,7 +221,7 @@ def run_batched(args):
         "dtype": "f32-updates/f64-pivots" if f.prec == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"batched-{len(xs)}-matern32", "instances": len(xs), "n_total": info["n"],
                    "nnz": nnz, "levels": info["nlevels"], "nrhs": 1, "rho": 3.0, "tuned_waves_per_block": wpb,
-                   "tuned_persist_max": pm, "graph": graph_s <= eager_s},
+                   "tuned_persist_max": pm, "tuned_unit_order": order, "graph": graph_s <= eager_s},
         "eager_ms": eager_s * 1e3, "graph_ms": graph_s * 1e3, "graph_nodes": ginfo["nodes"],
         "updates": st.updates, "host_analysis_s": t_analysis}), flush=True)
 
@@ -451,7 +453,7 @@ def main():
             "factor_only": {"value": nnz / tf, "unit": "S-entries/s", "ms": tf * 1e3},
             "solve_ms": ts * 1e3, "updates": r["updates"], "rank": r["rank"], "nonpositive": r["nonpositive"],
             "shifted": r["shifted"], "exp_hard": r["exp_hard"], "upload_s": r["t_upload"],
-            "workspace_bytes": r["workspace_bytes"],
+            "workspace_bytes": r["workspace_bytes"], "schedule": r["schedule"],
         }
         if r["refine"] is not None:
             entries[prec]["refine"] = r["refine"]
@@ -480,7 +482,7 @@ def main():
         "shifted": head["shifted"], "exp_hard": head["exp_hard"],
         "host_analysis_s": t_analysis, "host_analysis_split_s": [info["t_order_s"], info["t_pattern_s"],
                                                                  info["t_schedule_s"]],
-        "upload_s": head["upload_s"], "workspace_bytes": head["workspace_bytes"],
+        "upload_s": head["upload_s"], "workspace_bytes": head["workspace_bytes"], "schedule": head["schedule"],
     }
     if "refine" in head:
         result["refine"] = head["refine"]

@@ -59,6 +59,14 @@ typedef enum { KC_FP64 = 0, KC_MIXED = 1 } kc_prec;
  * SHIFT: a pivot p <= tau*Theta_jj is replaced by tau*Theta_jj. */
 typedef enum { KC_PIVOT_ZERO = 0, KC_PIVOT_SHIFT = 1 } kc_pivot;
 
+/* Order in which the factorization launches the work units of one DAG level
+ * (the columns of a level are independent, so results are the same in both).
+ * SPATIAL: the point cloud's k-d tree order, each XCD taking one contiguous
+ * slice of the level (L2 locality).  LONGEST: the unit with the longest walk
+ * first, so that the last, partly filled round of a level holds short units;
+ * this pays when levels are one to a few chip-fulls of wavefronts. */
+typedef enum { KC_ORDER_SPATIAL = 0, KC_ORDER_LONGEST = 1 } kc_unit_order;
+
 /* Matern covariance G_{l,nu}(x,y) of Section 4.4 with unit variance; nu must be
  * 0.5, 1.5 or 2.5 (closed forms), lengthscale > 0. */
 typedef struct {
@@ -201,18 +209,22 @@ void kc_factor_destroy(kc_factor *f);
  * whole, whose wavefronts stride over each level's units with a grid-wide
  * barrier between levels.  persist_max = 0 (the default) launches every level
  * separately; INT64_MAX runs the whole factorization in one persistent launch.
- * Results are bitwise identical for every schedule.  KC_EINVAL for wpb not in
- * {1, 2, 4}, persist_max < 0, or staged rows that do not fit in LDS. */
-kc_status kc_factor_set_schedule(kc_factor *f, int32_t wpb, int64_t persist_max);
-kc_status kc_factor_schedule(const kc_factor *f, int32_t *wpb, int64_t *persist_max);
+ * `order` is the order of the units within a level.  kc_factor_create picks
+ * the defaults: wpb from the mean column length, persist_max 0, and LONGEST
+ * when at least half of the units lie in levels of one to four chip-fulls,
+ * else SPATIAL.  Results are bitwise identical for every schedule.  KC_EINVAL
+ * for wpb not in {1, 2, 4}, persist_max < 0, an unknown order, or staged rows
+ * that do not fit in LDS.  Any pointer of kc_factor_schedule may be NULL. */
+kc_status kc_factor_set_schedule(kc_factor *f, int32_t wpb, int64_t persist_max, kc_unit_order order);
+kc_status kc_factor_schedule(const kc_factor *f, int32_t *wpb, int64_t *persist_max, kc_unit_order *order);
 
 /* Autotuner: times the factorization (reps repetitions after a warm-up) for
  * every schedule in {1, 2, 4} wavefronts per workgroup x level grouping
- * persist_max in {0, 256, 4096, all levels} -- skipping those whose staged rows
- * do not fit in LDS or whose persistent grid cannot be resident -- and keeps the
- * fastest for this factor (kc_factor_schedule reports it).  Results are bitwise
- * identical for every choice.  For a batch plan pass ell_dev (and ell is
- * ignored), else NULL. */
+ * persist_max in {0, 256, 4096, all levels} x unit order {SPATIAL, LONGEST} --
+ * skipping those whose staged rows do not fit in LDS or whose persistent grid
+ * cannot be resident -- and keeps the fastest for this factor
+ * (kc_factor_schedule reports it).  Results are bitwise identical for every
+ * choice.  For a batch plan pass ell_dev (and ell is ignored), else NULL. */
 kc_status kc_factor_tune(kc_factor *f, const double *x_dev, double nu, double ell, const double *ell_dev,
                          kc_pivot pivot, double tau, int32_t reps, void *stream, int32_t *chosen_wpb);
 

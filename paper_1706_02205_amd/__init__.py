@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 
@@ -25,6 +26,8 @@ __all__ = ["analyze", "analyze_supernodal", "analyze_batched", "dense_matvec", "
 _RULES = {"max": _lib.KC_RULE_MAX, "min": _lib.KC_RULE_MIN}
 _PRECS = {"fp64": _lib.KC_FP64, "mixed": _lib.KC_MIXED}
 _PIVOTS = {"zero": _lib.KC_PIVOT_ZERO, "shift": _lib.KC_PIVOT_SHIFT}
+_ORDERS = {"spatial": _lib.KC_ORDER_SPATIAL, "longest": _lib.KC_ORDER_LONGEST}
+_ORDER_NAMES = {v: k for k, v in _ORDERS.items()}
 
 
 def _ptr(a: np.ndarray):
@@ -224,17 +227,21 @@ class Factor:
                                               C.byref(w)), "kc_factor_tune")
         return int(w.value)
 
-    def set_schedule(self, wpb: int, persist_max: int) -> None:
-        """Wavefronts per workgroup (1, 2, 4) and the level grouping: runs of consecutive levels with at most
-        persist_max work units share one persistent launch (0: every level its own launch; 2**63 - 1: the
-        whole factorization in one launch)."""
-        _lib.check(_lib.load().kc_factor_set_schedule(self._h, int(wpb), int(persist_max)), "kc_factor_set_schedule")
+    def set_schedule(self, wpb: int, persist_max: int, order: Optional[str] = None) -> None:
+        """Wavefronts per workgroup (1, 2, 4), the level grouping (runs of consecutive levels with at most
+        persist_max work units share one persistent launch; 0: every level its own launch; 2**63 - 1: the
+        whole factorization in one launch) and the order of the units within a level ("spatial" or
+        "longest"; None keeps the current one)."""
+        if order is None:
+            order = self.schedule()[2]
+        _lib.check(_lib.load().kc_factor_set_schedule(self._h, int(wpb), int(persist_max), _ORDERS[order]),
+                   "kc_factor_set_schedule")
 
     def schedule(self) -> tuple:
-        """(wavefronts per workgroup, persist_max) in use -- the tuner's choice after tune()."""
-        w, pm = C.c_int32(), C.c_int64()
-        _lib.check(_lib.load().kc_factor_schedule(self._h, C.byref(w), C.byref(pm)), "kc_factor_schedule")
-        return int(w.value), int(pm.value)
+        """(wavefronts per workgroup, persist_max, unit order) in use -- the tuner's choice after tune()."""
+        w, pm, o = C.c_int32(), C.c_int64(), C.c_int()
+        _lib.check(_lib.load().kc_factor_schedule(self._h, C.byref(w), C.byref(pm), C.byref(o)), "kc_factor_schedule")
+        return int(w.value), int(pm.value), _ORDER_NAMES[int(o.value)]
 
     def capture(self, x_dev, b_dev, nu: float, lengthscale: float = 0.0, ell_dev=None, pivot: str = "zero",
                 tau: float = 0.0) -> "Graph":

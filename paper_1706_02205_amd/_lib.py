@@ -11,6 +11,7 @@ KC_OK, KC_EINVAL, KC_ENOMEM, KC_EWORKSPACE, KC_EHIP, KC_ESTATE, KC_ERANGE = rang
 KC_RULE_MAX, KC_RULE_MIN = 0, 1
 KC_FP64, KC_MIXED = 0, 1
 KC_PIVOT_ZERO, KC_PIVOT_SHIFT = 0, 1
+KC_ORDER_SPATIAL, KC_ORDER_LONGEST = 0, 1
 
 
 class kc_kernel(C.Structure):
@@ -90,8 +91,8 @@ def load():
         "kc_factor_tune": (C.c_int, [vp, vp, f64, f64, vp, C.c_int, f64, i32, vp, P(i32)]),
         "kc_graph_create": (C.c_int, [vp, vp, f64, f64, vp, C.c_int, f64, vp, vp, i32, vp, sz, P(vp)]),
         "kc_graph_launch": (C.c_int, [vp, vp]),
-        "kc_factor_set_schedule": (C.c_int, [vp, i32, C.c_int64]),
-        "kc_factor_schedule": (C.c_int, [vp, P(i32), P(C.c_int64)]),
+        "kc_factor_set_schedule": (C.c_int, [vp, i32, C.c_int64, C.c_int]),
+        "kc_factor_schedule": (C.c_int, [vp, P(i32), P(C.c_int64), P(C.c_int)]),
         "kc_graph_info": (C.c_int, [vp, P(C.c_int64), P(i32)]),
         "kc_graph_destroy": (None, [vp]),
         "kc_analyze_supernodal": (C.c_int, [vp, i64, i32, f64, i32, P(vp)]),

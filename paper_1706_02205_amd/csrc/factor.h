@@ -37,8 +37,10 @@ struct kc_factor {
     kc::Unit* units = nullptr;
     int64_t* unit_off_dev = nullptr;  // nlevels + 1, units of each level
     // block units of the factorization for 1, 2 and 4 wavefronts per workgroup:
-    // 64 * wpb consecutive entries of one column each, grouped by level
-    kc::Unit* bunits[3] = {nullptr, nullptr, nullptr};
+    // 64 * wpb consecutive entries of one column each, grouped by level, once in
+    // each unit order ([order][w], see kc_unit_order)
+    kc::Unit* bunits[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int32_t order = KC_ORDER_SPATIAL;  // kc_unit_order in use
     int64_t* boff_dev[3] = {nullptr, nullptr, nullptr};
     std::vector<int64_t> boff[3];
     int32_t* fwd_rows = nullptr;

@@ -25,6 +25,7 @@
 #include <atomic>
 #include <thread>
 #include <string>
+#include <system_error>
 #include <vector>
 
 #include "crmath.h"
@@ -762,7 +763,7 @@ BwdSchedule backward_schedule(const kc::Plan& p) {
 
 struct Layout {
     size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, cdelta, escptr, esc, L, Lcsc, diag,
-        units, unit_off, bunits[3], boff[3], fwd, bshort,
+        units, unit_off, bunits[2][3], boff[3], fwd, bshort,
         blong, bchunks, inst, total;
 };
 
@@ -797,7 +798,7 @@ Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
         const int per = kWave << w;
         size_t nb = 0;
         for (const Unit& u : p.units) nb += (u.first % per == 0);
-        o.bunits[w] = take(nb * sizeof(Unit));
+        for (int r = 0; r < 2; ++r) o.bunits[r][w] = take(nb * sizeof(Unit));
         o.boff[w] = take((size_t(p.nlevels) + 1) * sizeof(int64_t));
     }
     o.fwd = take(n * sizeof(int32_t));
@@ -823,13 +824,36 @@ int wpb_slot(int wpb) { return wpb == 4 ? 2 : wpb == 2 ? 1 : 0; }
 
 // Block units for `wpb` wavefronts per workgroup from the plan's 64-entry units
 // (each column's units are consecutive and start at entry 0).
-// Block units of each level, longest first.  A workgroup lasts as long as its
-// longest lane, whose walk is the prefix of row k before (k,j); workgroups of a
-// launch start in index order, so putting the longest first shortens the tail in
-// which a level's last workgroups leave most of the chip idle (on the 10^6-point
-// grid, 146.9 -> 138.7 ms in FP64).  The order of independent units does not
-// change any result.
-void block_units(const kc::Plan& p, int wpb, std::vector<Unit>& bu, std::vector<int64_t>& off) {
+// Sorts block units [b0, b1) (one level) by their longest lane, descending.
+void sort_longest_first(const kc::Plan& p, int per, std::vector<Unit>& bu, int64_t b0, int64_t b1,
+                        std::vector<std::pair<int64_t, Unit>>& tmp) {
+    tmp.clear();
+    for (int64_t t = b0; t < b1; ++t) {
+        const Unit un = bu[size_t(t)];
+        const int64_t e0 = p.colptr[size_t(un.col)] + un.first;
+        const int64_t e1 = std::min<int64_t>(e0 + per, p.colptr[size_t(un.col) + 1]);
+        int64_t w = 0;  // the longest walk: the prefix of row k before (k,j)
+        for (int64_t e = e0; e < e1; ++e)
+            w = std::max<int64_t>(w, int64_t(p.csc2csr[size_t(e)]) - p.rowptr[size_t(p.rowidx[size_t(e)])]);
+        tmp.push_back({w, un});
+    }
+    std::stable_sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (int64_t t = b0; t < b1; ++t) bu[size_t(t)] = tmp[size_t(t - b0)].second;
+}
+
+// Block units of each level in one of two orders (results are the same in both;
+// only the time differs).  Launches take them in plain block order.
+//  - KC_ORDER_SPATIAL: the plan's spatial (k-d tree) order, permuted so that the
+//    round-robin dealing of blocks gives each XCD one contiguous slice of the
+//    level (the map of xcd_block), whose L2 then serves one region of the points.
+//  - KC_ORDER_LONGEST: longest lane first.  A workgroup lasts as long as its
+//    longest lane, whose walk is the prefix of row k before (k,j), and workgroups
+//    start in index order, so the last, partly filled round of a level then holds
+//    the short units.  This pays when a level is one to a few chip-fulls of
+//    wavefronts (10^6-point grid: 146.9 -> 138.7 ms in FP64); with many rounds per
+//    level the lost L2 locality costs more.
+// Throws std::bad_alloc.
+void block_units(const kc::Plan& p, int wpb, int order, std::vector<Unit>& bu, std::vector<int64_t>& off) {
     const int per = kWave * wpb;
     bu.clear();
     off.assign(size_t(p.nlevels) + 1, 0);
@@ -838,30 +862,53 @@ void block_units(const kc::Plan& p, int wpb, std::vector<Unit>& bu, std::vector<
             if (p.units[size_t(u)].first % per == 0) bu.push_back(p.units[size_t(u)]);
         off[size_t(v) + 1] = int64_t(bu.size());
     }
+    // levels are handed out one at a time to up to 16 threads
     const int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
     std::atomic<int32_t> next{0};
+    std::atomic<bool> failed{false};
     auto work = [&]() {
-        std::vector<std::pair<int64_t, Unit>> tmp;
-        for (int32_t v; (v = next.fetch_add(1)) < p.nlevels;) {
-            const int64_t b0 = off[size_t(v)], b1 = off[size_t(v) + 1];
-            tmp.clear();
-            for (int64_t t = b0; t < b1; ++t) {
-                const Unit un = bu[size_t(t)];
-                const int64_t e0 = p.colptr[size_t(un.col)] + un.first;
-                const int64_t e1 = std::min<int64_t>(e0 + per, p.colptr[size_t(un.col) + 1]);
-                int64_t w = 0;
-                for (int64_t e = e0; e < e1; ++e)
-                    w = std::max<int64_t>(w, int64_t(p.csc2csr[size_t(e)]) - p.rowptr[size_t(p.rowidx[size_t(e)])]);
-                tmp.push_back({w, un});
+        try {
+            std::vector<std::pair<int64_t, Unit>> tmp;
+            std::vector<Unit> lvl;
+            for (int32_t v; !failed.load() && (v = next.fetch_add(1)) < p.nlevels;) {
+                const int64_t b0 = off[size_t(v)], b1 = off[size_t(v) + 1];
+                if (order == KC_ORDER_LONGEST) {
+                    sort_longest_first(p, per, bu, b0, b1, tmp);
+                } else {
+                    const int64_t nb = b1 - b0, q = nb / kNumXcd, r = nb % kNumXcd;
+                    lvl.assign(bu.begin() + b0, bu.begin() + b1);
+                    for (int64_t b = 0; b < nb; ++b) {
+                        const int64_t x = b % kNumXcd, i = b / kNumXcd;
+                        bu[size_t(b0 + b)] = lvl[size_t(x * q + std::min<int64_t>(x, r) + i)];
+                    }
+                }
             }
-            std::stable_sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
-            for (int64_t t = b0; t < b1; ++t) bu[size_t(t)] = tmp[size_t(t - b0)].second;
+        } catch (const std::bad_alloc&) {
+            failed = true;
         }
     };
     std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    try {
+        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    } catch (const std::system_error&) {
+        // fewer helpers: the calling thread takes whatever levels are left
+    }
     work();
     for (auto& th : pool) th.join();
+    if (failed) throw std::bad_alloc();
+}
+
+// The default unit order: longest first when at least half of the work units
+// lie in levels that fill the chip (8 wavefronts per SIMD) more than once and
+// at most four times.
+int32_t default_order(const kc::Plan& p, int num_cu) {
+    const int64_t slots = int64_t(std::max(1, num_cu)) * 4 * 8;
+    int64_t in = 0;
+    for (int32_t v = 0; v < p.nlevels; ++v) {
+        const int64_t c = p.unit_off[size_t(v) + 1] - p.unit_off[size_t(v)];
+        if (c > slots && c <= 4 * slots) in += c;
+    }
+    return 2 * in >= int64_t(p.units.size()) && in > 0 ? KC_ORDER_LONGEST : KC_ORDER_SPATIAL;
 }
 
 int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 2 + 15) / 16 * 16); }
@@ -920,7 +967,7 @@ kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int
     const int w = wpb_slot(WPB);
     if (!persistent) {
         if (ue <= ub) return KC_OK;
-        ichol_level<TN, C, VT, WPB><<<unsigned(ue - ub), WPB * kWave, lds, s>>>(a, f->bunits[w], ub, ue);
+        ichol_level<TN, C, VT, WPB><<<unsigned(ue - ub), WPB * kWave, lds, s>>>(a, f->bunits[f->order][w], ub, ue);
         KC_LAUNCH_CHECK();
         return KC_OK;
     }
@@ -934,7 +981,7 @@ kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int
     // every workgroup resident at once (the cooperative launch refuses anything larger)
     const unsigned blocks = unsigned(std::min<int64_t>(int64_t(per_cu) * f->num_cu, std::max<int64_t>(1, maxb)));
     IcholArgs<VT> av = a;
-    const Unit* bu = f->bunits[w];
+    const Unit* bu = f->bunits[f->order][w];
     const int64_t* bo = f->boff_dev[w];
     int l0v = l0, l1v = l1;
     void* args[] = {&av, &bu, &bo, &l0v, &l1v};
@@ -1362,7 +1409,7 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->units = reinterpret_cast<Unit*>(base + o.units);
     f->unit_off_dev = reinterpret_cast<int64_t*>(base + o.unit_off);
     for (int w = 0; w < 3; ++w) {
-        f->bunits[w] = reinterpret_cast<Unit*>(base + o.bunits[w]);
+        for (int r = 0; r < 2; ++r) f->bunits[r][w] = reinterpret_cast<Unit*>(base + o.bunits[r][w]);
         f->boff_dev[w] = reinterpret_cast<int64_t*>(base + o.boff[w]);
     }
     f->fwd_rows = reinterpret_cast<int32_t*>(base + o.fwd);
@@ -1394,14 +1441,21 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     KC_HIP(hipMemcpyAsync(f->units, p.units.data(), p.units.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->unit_off_dev, p.unit_off.data(), p.unit_off.size() * sizeof(int64_t),
                           hipMemcpyHostToDevice, s));
+    f->order = default_order(p, f->num_cu);
     for (int w = 0; w < 3; ++w) {
-        std::vector<Unit> bu;
-        block_units(p, 1 << w, bu, f->boff[w]);
-        if (!bu.empty())
-            KC_HIP(hipMemcpyAsync(f->bunits[w], bu.data(), bu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
+        for (int r = 0; r < 2; ++r) {
+            std::vector<Unit> bu;
+            try {
+                block_units(p, 1 << w, r, bu, f->boff[w]);
+            } catch (const std::bad_alloc&) {
+                return KC_ENOMEM;
+            }
+            if (!bu.empty())
+                KC_HIP(hipMemcpyAsync(f->bunits[r][w], bu.data(), bu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
+            KC_HIP(hipStreamSynchronize(s));  // bu is a local buffer
+        }
         KC_HIP(hipMemcpyAsync(f->boff_dev[w], f->boff[w].data(), f->boff[w].size() * sizeof(int64_t),
                               hipMemcpyHostToDevice, s));
-        KC_HIP(hipStreamSynchronize(s));  // bu is a local buffer
     }
     KC_HIP(hipMemcpyAsync(f->fwd_rows, p.fwd_rows.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!bs.shortc.empty())
@@ -1573,14 +1627,16 @@ kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double el
     KC_HIP(hipEventCreate(&b));
     int best = f->wpb;
     int64_t best_pm = f->persist_max;
+    int32_t best_order = f->order;
     float best_ms = 1e30f;
     // level grouping: levels with at most `pm` units share persistent launches
     const int64_t kGroupings[] = {0, 256, 4096, INT64_MAX};
     for (int wpb : {1, 2, 4}) {
         if (factor_lds(f, vt) > kMaxLdsBytes) continue;
-        for (int64_t pm : kGroupings) {
+        for (int64_t pm : kGroupings) for (int32_t order : {KC_ORDER_SPATIAL, KC_ORDER_LONGEST}) {
             f->wpb = wpb;
             f->persist_max = pm;
+            f->order = order;
             kc_status st = factorize_impl(f, x_dev, nu, ell, ell_dev, pivot, tau, 0, stream);  // warm-up
             if (st != KC_OK) {
                 // e.g. a persistent launch that does not fit: skip this grouping
@@ -1600,6 +1656,7 @@ kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double el
                 best_ms = ms;
                 best = wpb;
                 best_pm = pm;
+                best_order = order;
             }
         }
     }
@@ -1607,13 +1664,16 @@ kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double el
     (void)hipEventDestroy(b);
     f->wpb = best;
     f->persist_max = best_pm;
+    f->order = best_order;
     if (chosen_wpb) *chosen_wpb = best;
     return KC_OK;
 }
 
-kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max) {
-    if (!f || (wpb != 1 && wpb != 2 && wpb != 4) || persist_max < 0) {
-        kc::set_error("kc_factor_set_schedule: wavefronts per block must be 1, 2 or 4 and persist_max >= 0");
+kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max, kc_unit_order order) {
+    if (!f || (wpb != 1 && wpb != 2 && wpb != 4) || persist_max < 0 ||
+        (order != KC_ORDER_SPATIAL && order != KC_ORDER_LONGEST)) {
+        kc::set_error("kc_factor_set_schedule: wavefronts per block must be 1, 2 or 4, persist_max >= 0 and "
+                      "order SPATIAL or LONGEST");
         return KC_EINVAL;
     }
     const size_t vt = f->prec == KC_FP64 ? sizeof(double) : sizeof(float);
@@ -1623,13 +1683,15 @@ kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max)
     }
     f->wpb = wpb;
     f->persist_max = persist_max;
+    f->order = order;
     return KC_OK;
 }
 
-kc_status kc_factor_schedule(const kc_factor* f, int32_t* wpb, int64_t* persist_max) {
+kc_status kc_factor_schedule(const kc_factor* f, int32_t* wpb, int64_t* persist_max, kc_unit_order* order) {
     if (!f) return KC_EINVAL;
     if (wpb) *wpb = f->wpb;
     if (persist_max) *persist_max = f->persist_max;
+    if (order) *order = static_cast<kc_unit_order>(f->order);
     return KC_OK;
 }
 

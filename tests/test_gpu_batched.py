@@ -89,9 +89,9 @@ def test_tuner_choice_does_not_change_results(K, batch):
     base = f.export_L()
     wpb = f.tune(xd, 1.5, ell_dev=ed, reps=2)
     assert wpb in (1, 2, 4)
-    w2, pm = f.schedule()
-    print(f"[gpu] tuner chose wpb={w2} persist_max={pm}", flush=True)
-    assert w2 == wpb and pm in (0, 256, 4096, 2**63 - 1)
+    w2, pm, order = f.schedule()
+    print(f"[gpu] tuner chose wpb={w2} persist_max={pm} order={order}", flush=True)
+    assert w2 == wpb and pm in (0, 256, 4096, 2**63 - 1) and order in ("spatial", "longest")
     f.factorize_batched(xd, 1.5, ed)
     assert np.array_equal(f.export_L(), base)
 
@@ -99,26 +99,28 @@ def test_tuner_choice_does_not_change_results(K, batch):
 ALL_LEVELS = 2**63 - 1
 
 
-@pytest.mark.parametrize("wpb,persist_max", [(1, ALL_LEVELS), (4, ALL_LEVELS), (2, 3), (1, 40)])
-def test_persistent_schedules_bitwise(K, batch, wpb, persist_max):
+@pytest.mark.parametrize("wpb,persist_max,order", [(1, ALL_LEVELS, "spatial"), (4, ALL_LEVELS, "longest"),
+                                                   (2, 3, "longest"), (1, 40, "spatial"), (1, 0, "longest"),
+                                                   (2, 0, "spatial")])
+def test_persistent_schedules_bitwise(K, batch, wpb, persist_max, order):
     """Levels grouped into persistent launches (all levels in one launch, or runs of small levels
-    between per-level launches) give the per-level result bit for bit; a graph captured from such a
-    factor (which records per-level launches) replays the same result."""
-    print(f"[gpu] persistent schedule wpb={wpb} persist_max={persist_max}", flush=True)
+    between per-level launches), in either unit order, give the default schedule's result bit for bit;
+    a graph captured from such a factor (which records per-level launches) replays the same result."""
+    print(f"[gpu] schedule wpb={wpb} persist_max={persist_max} order={order}", flush=True)
     import torch
     xs, ells, ref, b = batch
     plan, f, xd, ed = run_batch(K, xs, ells)
     bd = dev(b)
     base_L = f.export_L()
     base_x = f.solve(bd).cpu().numpy()
-    f.set_schedule(wpb, persist_max)
-    assert f.schedule() == (wpb, persist_max)
+    f.set_schedule(wpb, persist_max, order)
+    assert f.schedule() == (wpb, persist_max, order)
     f.factorize_batched(xd, 1.5, ed)
     assert np.array_equal(f.export_L(), base_L)
     g = f.capture(xd, bd, 1.5, ell_dev=ed)
     info = g.info()
     print(f"[gpu] graph {info}", flush=True)
-    assert not info["persistent"] and f.schedule() == (wpb, persist_max)
+    assert not info["persistent"] and f.schedule() == (wpb, persist_max, order)
     for rep in range(2):
         out = g.launch()
         torch.cuda.synchronize()

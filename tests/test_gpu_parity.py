@@ -104,16 +104,18 @@ def test_index_gap_escapes_do_not_change_the_factor(K, limit, prec):
         assert np.array_equal(f.export_L(), R.L)
 
 
-@pytest.mark.parametrize("persist_max", [2**63 - 1, 16])
-def test_persistent_factorization_bitwise(K, persist_max):
-    """The whole factorization in one persistent launch (or its small levels grouped) equals the
-    oracle bit for bit, update counts included."""
-    print(f"[gpu] persistent factorization persist_max={persist_max}", flush=True)
+@pytest.mark.parametrize("persist_max,order", [(2**63 - 1, "spatial"), (16, "longest"), (0, "longest"),
+                                               (0, "spatial")])
+def test_schedules_factorization_bitwise(K, persist_max, order):
+    """The whole factorization in one persistent launch (or its small levels grouped), with the units
+    of a level in either order, equals the oracle bit for bit, update counts included."""
+    print(f"[gpu] factorization schedule persist_max={persist_max} order={order}", flush=True)
     w = W.small_uniform_2d()
     P, th, R = oracle_factor(w.points, w.rho, "max", w.nu, w.lengthscale)
     plan = K.analyze(w.points, w.rho)
     f = K.Factor(plan, "fp64")
-    f.set_schedule(4, persist_max)
+    f.set_schedule(4, persist_max, order)
+    assert f.schedule() == (4, persist_max, order)
     f.factorize(dev(w.points), w.nu, w.lengthscale, count_updates=True)
     st = f.stats()
     assert st.updates == R.updates and st.nonpositive == R.nonpositive
