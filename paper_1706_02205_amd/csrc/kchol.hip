@@ -824,65 +824,22 @@ int wpb_slot(int wpb) { return wpb == 4 ? 2 : wpb == 2 ? 1 : 0; }
 
 // Block units for `wpb` wavefronts per workgroup from the plan's 64-entry units
 // (each column's units are consecutive and start at entry 0).
-// Sorts block units [b0, b1) (one level) by their longest lane, descending.
-void sort_longest_first(const kc::Plan& p, int per, std::vector<Unit>& bu, int64_t b0, int64_t b1,
-                        std::vector<std::pair<int64_t, Unit>>& tmp) {
-    tmp.clear();
-    for (int64_t t = b0; t < b1; ++t) {
-        const Unit un = bu[size_t(t)];
-        const int64_t e0 = p.colptr[size_t(un.col)] + un.first;
-        const int64_t e1 = std::min<int64_t>(e0 + per, p.colptr[size_t(un.col) + 1]);
-        int64_t w = 0;  // the longest walk: the prefix of row k before (k,j)
-        for (int64_t e = e0; e < e1; ++e)
-            w = std::max<int64_t>(w, int64_t(p.csc2csr[size_t(e)]) - p.rowptr[size_t(p.rowidx[size_t(e)])]);
-        tmp.push_back({w, un});
-    }
-    std::stable_sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
-    for (int64_t t = b0; t < b1; ++t) bu[size_t(t)] = tmp[size_t(t - b0)].second;
-}
+// Wavefronts of the factorization the device holds at once (8 per SIMD).
+int64_t resident_waves(int num_cu) { return int64_t(std::max(1, num_cu)) * 4 * 8; }
 
-// Block units of each level in one of two orders (results are the same in both;
-// only the time differs).  Launches take them in plain block order.
-//  - KC_ORDER_SPATIAL: the plan's spatial (k-d tree) order, permuted so that the
-//    round-robin dealing of blocks gives each XCD one contiguous slice of the
-//    level (the map of xcd_block), whose L2 then serves one region of the points.
-//  - KC_ORDER_LONGEST: longest lane first.  A workgroup lasts as long as its
-//    longest lane, whose walk is the prefix of row k before (k,j), and workgroups
-//    start in index order, so the last, partly filled round of a level then holds
-//    the short units.  This pays when a level is one to a few chip-fulls of
-//    wavefronts (10^6-point grid: 146.9 -> 138.7 ms in FP64); with many rounds per
-//    level the lost L2 locality costs more.
-// Throws std::bad_alloc.
-void block_units(const kc::Plan& p, int wpb, int order, std::vector<Unit>& bu, std::vector<int64_t>& off) {
-    const int per = kWave * wpb;
-    bu.clear();
-    off.assign(size_t(p.nlevels) + 1, 0);
-    for (int32_t v = 0; v < p.nlevels; ++v) {
-        for (int64_t u = p.unit_off[size_t(v)]; u < p.unit_off[size_t(v) + 1]; ++u)
-            if (p.units[size_t(u)].first % per == 0) bu.push_back(p.units[size_t(u)]);
-        off[size_t(v) + 1] = int64_t(bu.size());
-    }
-    // levels are handed out one at a time to up to 16 threads
-    const int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+// Runs fn(v) for every level v, the levels handed out one at a time to up to 16
+// threads (one thread for small plans).  fn may throw std::bad_alloc, which is
+// rethrown here.
+template <typename Fn>
+void for_levels(const kc::Plan& p, Fn fn) {
+    const int nt = p.nnz() < (int64_t(1) << 22)
+                       ? 1
+                       : int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
     std::atomic<int32_t> next{0};
     std::atomic<bool> failed{false};
     auto work = [&]() {
         try {
-            std::vector<std::pair<int64_t, Unit>> tmp;
-            std::vector<Unit> lvl;
-            for (int32_t v; !failed.load() && (v = next.fetch_add(1)) < p.nlevels;) {
-                const int64_t b0 = off[size_t(v)], b1 = off[size_t(v) + 1];
-                if (order == KC_ORDER_LONGEST) {
-                    sort_longest_first(p, per, bu, b0, b1, tmp);
-                } else {
-                    const int64_t nb = b1 - b0, q = nb / kNumXcd, r = nb % kNumXcd;
-                    lvl.assign(bu.begin() + b0, bu.begin() + b1);
-                    for (int64_t b = 0; b < nb; ++b) {
-                        const int64_t x = b % kNumXcd, i = b / kNumXcd;
-                        bu[size_t(b0 + b)] = lvl[size_t(x * q + std::min<int64_t>(x, r) + i)];
-                    }
-                }
-            }
+            for (int32_t v; !failed.load() && (v = next.fetch_add(1)) < p.nlevels;) fn(v);
         } catch (const std::bad_alloc&) {
             failed = true;
         }
@@ -898,11 +855,86 @@ void block_units(const kc::Plan& p, int wpb, int order, std::vector<Unit>& bu, s
     if (failed) throw std::bad_alloc();
 }
 
+// The longest walk of each work unit (64 entries of a column): the longest
+// prefix of row k before (k,j) over its entries.  A wavefront lasts about as
+// long as its longest lane.  Throws std::bad_alloc.
+std::vector<int32_t> unit_walks(const kc::Plan& p) {
+    std::vector<int32_t> walk(p.units.size());
+    for_levels(p, [&](int32_t v) {
+        for (int64_t u = p.unit_off[size_t(v)]; u < p.unit_off[size_t(v) + 1]; ++u) {
+            const Unit un = p.units[size_t(u)];
+            const int64_t e0 = p.colptr[size_t(un.col)] + un.first;
+            const int64_t e1 = std::min<int64_t>(e0 + kWave, p.colptr[size_t(un.col) + 1]);
+            int64_t w = 0;
+            for (int64_t e = e0; e < e1; ++e)
+                w = std::max<int64_t>(w, int64_t(p.csc2csr[size_t(e)]) - p.rowptr[size_t(p.rowidx[size_t(e)])]);
+            walk[size_t(u)] = int32_t(std::min<int64_t>(w, INT32_MAX));
+        }
+    });
+    return walk;
+}
+
+// Block units of each level in one of two orders (results are the same in both;
+// only the time differs).  Launches take them in plain block order.
+//  - KC_ORDER_SPATIAL: the plan's spatial (k-d tree) order, permuted so that the
+//    round-robin dealing of blocks gives each XCD one contiguous slice of the
+//    level (the map of xcd_block), whose L2 then serves one region of the points.
+//  - KC_ORDER_LONGEST: longest walk first (`walk` from unit_walks; a block unit
+//    takes the longest of its wavefronts).  A workgroup lasts as long as its
+//    longest lane and workgroups start in index order, so the last, partly
+//    filled round of a level then holds the short units.  This pays when a level
+//    is one to a few chip-fulls of wavefronts (10^6-point grid: 146.9 -> 138.7 ms
+//    in FP64); with many rounds per level the lost L2 locality costs more.
+// Throws std::bad_alloc.
+void block_units(const kc::Plan& p, int wpb, int order, const std::vector<int32_t>& walk, std::vector<Unit>& bu,
+                 std::vector<int64_t>& off) {
+    const int per = kWave * wpb;
+    std::vector<int32_t> key;
+    bu.clear();
+    off.assign(size_t(p.nlevels) + 1, 0);
+    for (int32_t v = 0; v < p.nlevels; ++v) {
+        for (int64_t u = p.unit_off[size_t(v)]; u < p.unit_off[size_t(v) + 1]; ++u) {
+            const Unit un = p.units[size_t(u)];
+            const int32_t w = order == KC_ORDER_LONGEST ? walk[size_t(u)] : 0;
+            if (un.first % per == 0) {
+                bu.push_back(un);
+                key.push_back(w);
+            } else if (!bu.empty() && bu.back().col == un.col) {
+                key.back() = std::max(key.back(), w);  // a later wavefront of the same block unit
+            }
+        }
+        off[size_t(v) + 1] = int64_t(bu.size());
+    }
+    for_levels(p, [&](int32_t v) {
+        const int64_t b0 = off[size_t(v)], b1 = off[size_t(v) + 1], nb = b1 - b0;
+        std::vector<std::pair<int32_t, Unit>> lvl;
+        lvl.reserve(size_t(nb));
+        for (int64_t t = b0; t < b1; ++t) lvl.push_back({key[size_t(t)], bu[size_t(t)]});
+        if (order == KC_ORDER_LONGEST) {
+            std::stable_sort(lvl.begin(), lvl.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+            for (int64_t t = 0; t < nb; ++t) bu[size_t(b0 + t)] = lvl[size_t(t)].second;
+        } else {
+            const int64_t q = nb / kNumXcd, r = nb % kNumXcd;
+            for (int64_t b = 0; b < nb; ++b) {
+                const int64_t x = b % kNumXcd, i = b / kNumXcd;
+                bu[size_t(b0 + b)] = lvl[size_t(x * q + std::min<int64_t>(x, r) + i)].second;
+            }
+        }
+    });
+}
+
+// Whether the unit order can matter at all: only a level with more units than
+// the device holds at once has a last, partly filled round.
+bool order_matters(const kc::Plan& p, int num_cu) {
+    for (int32_t v = 0; v < p.nlevels; ++v)
+        if (p.unit_off[size_t(v) + 1] - p.unit_off[size_t(v)] > resident_waves(num_cu)) return true;
+    return false;
+}
+
 // The default unit order: longest first when at least half of the work units
-// lie in levels that fill the chip (8 wavefronts per SIMD) more than once and
-// at most four times.
+// lie in levels that fill the chip more than once and at most four times.
 int32_t default_order(const kc::Plan& p, int num_cu) {
-    const int64_t slots = int64_t(std::max(1, num_cu)) * 4 * 8;
+    const int64_t slots = resident_waves(num_cu);
     int64_t in = 0;
     for (int32_t v = 0; v < p.nlevels; ++v) {
         const int64_t c = p.unit_off[size_t(v) + 1] - p.unit_off[size_t(v)];
@@ -1441,12 +1473,21 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     KC_HIP(hipMemcpyAsync(f->units, p.units.data(), p.units.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
     KC_HIP(hipMemcpyAsync(f->unit_off_dev, p.unit_off.data(), p.unit_off.size() * sizeof(int64_t),
                           hipMemcpyHostToDevice, s));
+    // both unit orders, unless no level exceeds what the device holds at once
+    // (then the order cannot matter, and LONGEST shares SPATIAL's arrays)
     f->order = default_order(p, f->num_cu);
+    const bool both = order_matters(p, f->num_cu);
+    std::vector<int32_t> walk;
+    try {
+        if (both) walk = unit_walks(p);
+    } catch (const std::bad_alloc&) {
+        return KC_ENOMEM;
+    }
     for (int w = 0; w < 3; ++w) {
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < (both ? 2 : 1); ++r) {
             std::vector<Unit> bu;
             try {
-                block_units(p, 1 << w, r, bu, f->boff[w]);
+                block_units(p, 1 << w, r, walk, bu, f->boff[w]);
             } catch (const std::bad_alloc&) {
                 return KC_ENOMEM;
             }
@@ -1454,6 +1495,7 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
                 KC_HIP(hipMemcpyAsync(f->bunits[r][w], bu.data(), bu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
             KC_HIP(hipStreamSynchronize(s));  // bu is a local buffer
         }
+        if (!both) f->bunits[KC_ORDER_LONGEST][w] = f->bunits[KC_ORDER_SPATIAL][w];
         KC_HIP(hipMemcpyAsync(f->boff_dev[w], f->boff[w].data(), f->boff[w].size() * sizeof(int64_t),
                               hipMemcpyHostToDevice, s));
     }

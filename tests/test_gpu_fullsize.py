@@ -10,7 +10,8 @@ samples one by one and properties that hold at any size:
   bitwise the oracle's, computed in the same per-entry order;
 * (L L^T)_ab = Theta_ab on sampled entries of S (the defining IC(0) identity),
   to 1e-12 relative to Theta_aa = 1;
-* the solve's componentwise backward error |Pb - L L^T x| <= 1e-10 |L| |L^T| |x|.
+* the solve's componentwise backward error |Pb - L L^T x| <= 1e-10 |L| |L^T| |x|;
+* both orders of the units within a level give the same L bit for bit.
 """
 import numpy as np
 import pytest
@@ -42,7 +43,7 @@ def big():
     L = f.export_L()
     print("[gpu] full size: factor exported", flush=True)
     return dict(w=w, perm=perm, l=l, colptr=colptr, rowidx=rowidx, xh=np.ascontiguousarray(w.points[perm]),
-                L=L, b=b, x=x, st=st)
+                L=L, b=b, x=x, st=st, f=f, xd=xd)
 
 
 def test_ordering_and_pattern_samples(big):
@@ -64,6 +65,19 @@ def test_leading_columns_bitwise(big):
     ref = O.ichol_leading(cp, ri, m, th)
     assert np.array_equal(big["L"][:cp[m]], ref)
     assert big["st"].exp_hard == 0 and big["st"].nonpositive == 0
+
+
+def test_unit_orders_bitwise_at_full_size(big):
+    """Most levels here hold one to four chip-fulls of wavefronts, so the default launches the units of
+    a level longest first; the spatial order gives the same L bit for bit."""
+    f = big["f"]
+    wpb, pm, order = f.schedule()
+    assert order == "longest"
+    print("[gpu] full size: spatial unit order", flush=True)
+    f.set_schedule(wpb, pm, "spatial")
+    f.factorize(big["xd"], big["w"].nu, big["w"].lengthscale)
+    assert np.array_equal(f.export_L(), big["L"])
+    f.set_schedule(wpb, pm, order)
 
 
 def test_ic0_identity_on_sampled_entries(big):
