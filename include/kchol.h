@@ -211,7 +211,7 @@ void kc_factor_destroy(kc_factor *f);
  * separately; INT64_MAX runs the whole factorization in one persistent launch.
  * `order` is the order of the units within a level.  kc_factor_create picks
  * the defaults: wpb from the mean column length, persist_max 0, and LONGEST
- * when at least half of the units lie in levels of one to four chip-fulls,
+ * when at least half of the units lie in levels of 8 to 32 wavefronts per SIMD,
  * else SPATIAL.  Results are bitwise identical for every schedule.  KC_EINVAL
  * for wpb not in {1, 2, 4}, persist_max < 0, an unknown order, or staged rows
  * that do not fit in LDS.  Any pointer of kc_factor_schedule may be NULL. */

@@ -824,8 +824,9 @@ int wpb_slot(int wpb) { return wpb == 4 ? 2 : wpb == 2 ? 1 : 0; }
 
 // Block units for `wpb` wavefronts per workgroup from the plan's 64-entry units
 // (each column's units are consecutive and start at entry 0).
-// Wavefronts of the factorization the device holds at once (8 per SIMD).
-int64_t resident_waves(int num_cu) { return int64_t(std::max(1, num_cu)) * 4 * 8; }
+// 8 wavefronts per SIMD of the device: the unit of level size in the choices
+// below (the factorization kernel itself holds fewer, 5 per SIMD in FP64).
+int64_t waves_at_8_per_simd(int num_cu) { return int64_t(std::max(1, num_cu)) * 4 * 8; }
 
 // Runs fn(v) for every level v, the levels handed out one at a time to up to 16
 // threads (one thread for small plans).  fn may throw std::bad_alloc, which is
@@ -924,17 +925,20 @@ void block_units(const kc::Plan& p, int wpb, int order, const std::vector<int32_
 }
 
 // Whether the unit order can matter at all: only a level with more units than
-// the device holds at once has a last, partly filled round.
+// the device holds at once has a last, partly filled round (8 per SIMD bounds
+// what it holds).
 bool order_matters(const kc::Plan& p, int num_cu) {
     for (int32_t v = 0; v < p.nlevels; ++v)
-        if (p.unit_off[size_t(v) + 1] - p.unit_off[size_t(v)] > resident_waves(num_cu)) return true;
+        if (p.unit_off[size_t(v) + 1] - p.unit_off[size_t(v)] > waves_at_8_per_simd(num_cu)) return true;
     return false;
 }
 
 // The default unit order: longest first when at least half of the work units
-// lie in levels that fill the chip more than once and at most four times.
+// lie in levels of more than 8 and at most 32 wavefronts per SIMD (the FP64
+// kernel holds 5 per SIMD, so such a level runs as two to seven rounds, and its
+// last, partly filled round is a large share of its time).
 int32_t default_order(const kc::Plan& p, int num_cu) {
-    const int64_t slots = resident_waves(num_cu);
+    const int64_t slots = waves_at_8_per_simd(num_cu);
     int64_t in = 0;
     for (int32_t v = 0; v < p.nlevels; ++v) {
         const int64_t c = p.unit_off[size_t(v) + 1] - p.unit_off[size_t(v)];
