@@ -193,6 +193,20 @@ kc_status kc_solve_bytes(const kc_factor *f, int32_t nrhs, size_t *bytes);
 kc_status kc_solve(const kc_factor *f, const double *b_dev, double *x_dev, int32_t nrhs, void *scratch_dev,
                    size_t scratch_bytes, void *stream);
 
+/* kc_factorize followed by kc_solve (Section 2.2 and Section 1, task (2)) in one
+ * call, with the forward sweep overlapped with the factorization: after the
+ * launch covering factor levels [l0, l1) is enqueued on `stream`, a second
+ * stream owned by the factor (created on first use, default priority; it waits
+ * on an event recorded on `stream`) runs the forward sweep of those levels,
+ * while `stream` goes on with the next levels; the backward sweep runs on
+ * `stream` after both.  Results are bitwise those of kc_factorize + kc_solve.
+ * Arguments as for those calls (update counting is not offered); single
+ * problems only (KC_EINVAL for a batch plan).  All work is ordered after
+ * earlier work on `stream`, and later work on `stream` is ordered after it. */
+kc_status kc_factorize_solve(kc_factor *f, const double *x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
+                             const double *b_dev, double *x_out, int32_t nrhs, void *scratch_dev, size_t scratch_bytes,
+                             void *stream);
+
 /* Synchronises the factor's last stream and reports pivot statistics. */
 kc_status kc_factor_stats(kc_factor *f, kc_factor_stats_t *stats);
 

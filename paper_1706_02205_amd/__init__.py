@@ -217,8 +217,8 @@ class Factor:
 
     def tune(self, x_dev, nu: float, lengthscale: float = 0.0, ell_dev=None, pivot: str = "zero", tau: float = 0.0,
              reps: int = 3, stream=None) -> int:
-        """Pick the fastest schedule (wavefronts per workgroup x level grouping) for this factor by timing it;
-        returns the wavefronts per workgroup (schedule() gives both)."""
+        """Pick the fastest schedule (wavefronts per workgroup x level grouping x unit order) for this factor by
+        timing it; returns the wavefronts per workgroup (schedule() gives all three)."""
         self._check_points(x_dev)
         w = C.c_int32()
         _lib.check(_lib.load().kc_factor_tune(self._h, C.c_void_p(x_dev.data_ptr()), float(nu), float(lengthscale),
@@ -256,6 +256,29 @@ class Factor:
         _lib.check(_lib.load().kc_theta(self._h, C.c_void_p(x_dev.data_ptr()), _lib.kc_kernel(nu, lengthscale),
                                         C.c_void_p(out.data_ptr()), _stream_ptr(stream)), "kc_theta")
         return out
+
+    def factorize_solve(self, x_dev, b_dev, nu: float, lengthscale: float, pivot: str = "zero", tau: float = 0.0,
+                        out=None, stream=None):
+        """factorize() then solve() in one call, the forward sweep overlapped with the factorization on a
+        second stream; bitwise the same result.  Returns x."""
+        import torch
+        self._check_points(x_dev)
+        if b_dev.dtype != torch.float64 or not b_dev.is_cuda or not b_dev.is_contiguous():
+            raise ValueError("b must be a contiguous float64 CUDA tensor")
+        if b_dev.shape[0] != self.n:
+            raise ValueError("b must have n rows")
+        nrhs = 1 if b_dev.dim() == 1 else int(b_dev.shape[1])
+        x = out if out is not None else torch.empty_like(b_dev)
+        nb = C.c_size_t()
+        _lib.check(_lib.load().kc_solve_bytes(self._h, nrhs, C.byref(nb)), "kc_solve_bytes")
+        need = int(nb.value)
+        if self._scratch is None or self._scratch.numel() < need:
+            self._scratch = torch.empty(need, dtype=torch.uint8, device=b_dev.device)
+        _lib.check(_lib.load().kc_factorize_solve(self._h, C.c_void_p(x_dev.data_ptr()), _lib.kc_kernel(nu, lengthscale),
+                                                  _PIVOTS[pivot], float(tau), C.c_void_p(b_dev.data_ptr()),
+                                                  C.c_void_p(x.data_ptr()), nrhs, C.c_void_p(self._scratch.data_ptr()),
+                                                  self._scratch.numel(), _stream_ptr(stream)), "kc_factorize_solve")
+        return x
 
     def solve(self, b_dev, out=None, stream=None):
         """x = P^T L^-T L^-1 P b for b of shape (n,) or (n, nrhs), original order."""

@@ -38,7 +38,7 @@ class kc_factor_stats_t(C.Structure):
 
 EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "kc_plan_export", "kc_plan_levels", "kc_plan_set_delta_limit",
             "kc_plan_destroy", "kc_factor_bytes", "kc_factor_create", "kc_factorize", "kc_theta", "kc_solve_bytes",
-            "kc_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
+            "kc_solve", "kc_factorize_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
             "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
             "kc_factor_tune", "kc_factor_set_schedule", "kc_factor_schedule", "kc_graph_create", "kc_graph_info", "kc_graph_launch", "kc_graph_destroy", "kc_analyze_supernodal",
             "kc_plan_supernodes")
@@ -79,6 +79,7 @@ def load():
         "kc_theta": (C.c_int, [vp, vp, kc_kernel, vp, vp]),
         "kc_solve_bytes": (C.c_int, [vp, i32, P(sz)]),
         "kc_solve": (C.c_int, [vp, vp, vp, i32, vp, sz, vp]),
+        "kc_factorize_solve": (C.c_int, [vp, vp, kc_kernel, C.c_int, f64, vp, vp, i32, vp, sz, vp]),
         "kc_factor_stats": (C.c_int, [vp, P(kc_factor_stats_t)]),
         "kc_factor_export_L": (C.c_int, [vp, vp]),
         "kc_factor_destroy": (None, [vp]),

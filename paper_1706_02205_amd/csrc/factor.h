@@ -55,4 +55,7 @@ struct kc_factor {
     bool factorized = false;
     bool counted = false;
     hipStream_t last = nullptr;
+    // second stream and its event for kc_factorize_solve (created on first use)
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_ev = nullptr;
 };

@@ -26,6 +26,7 @@
 #include <thread>
 #include <string>
 #include <system_error>
+#include <type_traits>
 #include <vector>
 
 #include "crmath.h"
@@ -1033,11 +1034,16 @@ kc_status launch_wpb(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int
     return launch_one<TN, C, VT, 1>(f, a, ub, ue, l0, l1, maxu, persistent, s);
 }
 
+struct NoAfter {
+    kc_status operator()(int, int) const { return KC_OK; }
+};
+
 // The levels of the factorization: a level with more than f->persist_max units is
 // its own launch; each run of consecutive smaller levels is one persistent launch.
-template <typename VT>
+// after(l0, l1) is called once the launch covering levels [l0, l1) is enqueued.
+template <typename VT, typename After = NoAfter>
 kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const double* ells, int pol, double tau,
-                        hipStream_t s) {
+                        hipStream_t s, After after = After()) {
     const IcholArgs<VT> a = ichol_args<VT>(f, ell, ells, pol, tau);
     auto go = [&](int64_t ub, int64_t ue, int l0, int l1, int64_t maxu, bool persistent) {
         if (cnt) {
@@ -1055,7 +1061,8 @@ kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const 
     while (v < nl) {
         const int64_t cnt_v = f->unit_off[v + 1] - f->unit_off[v];  // 64-entry units: the grouping criterion
         if (cnt_v > f->persist_max) {
-            const kc_status st = go(bo[v], bo[v + 1], v, v + 1, bo[v + 1] - bo[v], false);
+            kc_status st = go(bo[v], bo[v + 1], v, v + 1, bo[v + 1] - bo[v], false);
+            if (st == KC_OK) st = after(v, v + 1);
             if (st != KC_OK) return st;
             ++v;
             continue;
@@ -1066,26 +1073,33 @@ kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const 
             maxb = std::max<int64_t>(maxb, bo[w + 1] - bo[w]);
             ++w;
         }
-        const kc_status st = maxb > 0 ? go(0, 0, v, w, maxb, true) : KC_OK;  // a run of empty levels needs nothing
+        kc_status st = maxb > 0 ? go(0, 0, v, w, maxb, true) : KC_OK;  // a run of empty levels needs nothing
+        if (st == KC_OK) st = after(v, w);
         if (st != KC_OK) return st;
         v = w;
     }
     return KC_OK;
 }
 
+// Forward sweep of levels [l0, l1): y = L^-1 P b for right-hand sides r0 .. r0+NR-1.
 template <typename VT, int NR>
-kc_status solve_pass(const kc_factor* f, const double* b, double* x, int ld, int r0, double* y, double* partial,
+kc_status fwd_levels(const kc_factor* f, const double* b, int ld, int r0, double* y, size_t l0, size_t l1,
                      hipStream_t s) {
     const VT* Lv = static_cast<const VT*>(f->L);
-    const VT* Lc = static_cast<const VT*>(f->Lcsc);
-    const size_t nl = f->fwd_off.size() - 1;
-    for (size_t v = 0; v < nl; ++v) {
+    for (size_t v = l0; v < l1; ++v) {
         const int64_t rb = f->fwd_off[v], re = f->fwd_off[v + 1];
         if (re <= rb) continue;
         fwd_solve<VT, NR><<<grid_for(re - rb, kWavesPerBlock), kBlock, 0, s>>>(
             f->fwd_rows, rb, re, f->rowptr, f->rowend, f->colidx, Lv, f->diag, f->perm, b, ld, r0, y);
         KC_LAUNCH_CHECK();
     }
+    return KC_OK;
+}
+
+// Backward sweep: x = P^T L^-T y for right-hand sides r0 .. r0+NR-1.
+template <typename VT, int NR>
+kc_status bwd_levels(const kc_factor* f, double* x, int ld, int r0, double* y, double* partial, hipStream_t s) {
+    const VT* Lc = static_cast<const VT*>(f->Lcsc);
     const size_t nr = f->short_off.size() - 1;
     for (size_t v = 0; v < nr; ++v) {
         const int64_t sb = f->short_off[v], se = f->short_off[v + 1];
@@ -1108,25 +1122,68 @@ kc_status solve_pass(const kc_factor* f, const double* b, double* x, int ld, int
     return KC_OK;
 }
 
-template <typename VT>
-kc_status solve_typed(const kc_factor* f, const double* b, double* x, int nrhs, double* y, double* partial,
-                      hipStream_t s) {
+// Calls fn(std::integral_constant<int, NR>(), r0) for each pass of at most
+// kMaxRhsPerPass right-hand sides, NR being the pass's width.
+template <typename Fn>
+kc_status for_passes(int nrhs, Fn fn) {
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPerPass) {
         const int nr = std::min(kMaxRhsPerPass, nrhs - r0);
         kc_status st;
         switch (nr) {
-            case 1: st = solve_pass<VT, 1>(f, b, x, nrhs, r0, y, partial, s); break;
-            case 2: st = solve_pass<VT, 2>(f, b, x, nrhs, r0, y, partial, s); break;
-            case 3: st = solve_pass<VT, 3>(f, b, x, nrhs, r0, y, partial, s); break;
-            case 4: st = solve_pass<VT, 4>(f, b, x, nrhs, r0, y, partial, s); break;
-            case 5: st = solve_pass<VT, 5>(f, b, x, nrhs, r0, y, partial, s); break;
-            case 6: st = solve_pass<VT, 6>(f, b, x, nrhs, r0, y, partial, s); break;
-            case 7: st = solve_pass<VT, 7>(f, b, x, nrhs, r0, y, partial, s); break;
-            default: st = solve_pass<VT, 8>(f, b, x, nrhs, r0, y, partial, s); break;
+            case 1: st = fn(std::integral_constant<int, 1>(), r0); break;
+            case 2: st = fn(std::integral_constant<int, 2>(), r0); break;
+            case 3: st = fn(std::integral_constant<int, 3>(), r0); break;
+            case 4: st = fn(std::integral_constant<int, 4>(), r0); break;
+            case 5: st = fn(std::integral_constant<int, 5>(), r0); break;
+            case 6: st = fn(std::integral_constant<int, 6>(), r0); break;
+            case 7: st = fn(std::integral_constant<int, 7>(), r0); break;
+            default: st = fn(std::integral_constant<int, 8>(), r0); break;
         }
         if (st != KC_OK) return st;
     }
     return KC_OK;
+}
+
+template <typename VT>
+kc_status solve_typed(const kc_factor* f, const double* b, double* x, int nrhs, double* y, double* partial,
+                      hipStream_t s) {
+    const size_t nl = f->fwd_off.size() - 1;
+    return for_passes(nrhs, [&](auto w, int r0) {
+        constexpr int NR = decltype(w)::value;
+        const kc_status st = fwd_levels<VT, NR>(f, b, nrhs, r0, y, 0, nl, s);
+        return st != KC_OK ? st : bwd_levels<VT, NR>(f, x, nrhs, r0, y, partial, s);
+    });
+}
+
+// Factorization and solve with the forward sweep overlapped: once the launch
+// covering factor levels [l0, l1) is enqueued on s, an event recorded after it
+// lets the second stream `aux` run the forward sweep of the same levels while s
+// goes on with the next factor levels.  A row of level v reads only L entries of
+// columns at levels <= v and y of rows at levels < v, and no later factor level
+// writes them, so the two streams never touch the same data out of order.  The
+// backward sweep needs the whole factor and runs on s after both.
+template <typename VT>
+kc_status factorize_solve_typed(kc_factor* f, int tn, double ell, int pol, double tau, const double* b, double* x,
+                                int nrhs, double* y, double* partial, hipStream_t s) {
+    hipStream_t aux = f->aux;
+    hipEvent_t ev = f->aux_ev;
+    auto after = [&](int l0, int l1) -> kc_status {
+        KC_HIP(hipEventRecord(ev, s));
+        KC_HIP(hipStreamWaitEvent(aux, ev, 0));
+        return for_passes(nrhs, [&](auto w, int r0) {
+            constexpr int NR = decltype(w)::value;
+            return fwd_levels<VT, NR>(f, b, nrhs, r0, y, size_t(l0), size_t(l1), aux);
+        });
+    };
+    kc_status st = launch_levels<VT>(f, tn, false, ell, nullptr, pol, tau, s, after);
+    // whatever was enqueued on aux must finish before s goes on, also after an error
+    KC_HIP(hipEventRecord(ev, aux));
+    KC_HIP(hipStreamWaitEvent(s, ev, 0));
+    if (st != KC_OK) return st;
+    return for_passes(nrhs, [&](auto w, int r0) {
+        constexpr int NR = decltype(w)::value;
+        return bwd_levels<VT, NR>(f, x, nrhs, r0, y, partial, s);
+    });
 }
 
 size_t solve_scratch_bytes(const kc_factor* f, int32_t nrhs) {
@@ -1624,6 +1681,61 @@ kc_status kc_solve(const kc_factor* f, const double* b_dev, double* x_dev, int32
     return st;
 }
 
+kc_status kc_factorize_solve(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
+                             const double* b_dev, double* x_out, int32_t nrhs, void* scratch_dev, size_t scratch_bytes,
+                             void* stream) {
+    if (!f || !x_dev || !b_dev || !x_out || !scratch_dev || nrhs < 1) return KC_EINVAL;
+    if (f->ninst > 1) {
+        kc::set_error("kc_factorize_solve: the plan holds a batch; use kc_factorize_batched and kc_solve");
+        return KC_EINVAL;
+    }
+    if (b_dev == x_out) {
+        kc::set_error("kc_factorize_solve: b and x must not alias");
+        return KC_EINVAL;
+    }
+    const int tn = twonu_of(kernel.nu);
+    if (!tn || !(kernel.lengthscale > 0.0) || !std::isfinite(kernel.lengthscale)) {
+        kc::set_error("kc_factorize_solve: nu must be 0.5, 1.5 or 2.5 and the lengthscale finite and positive");
+        return KC_EINVAL;
+    }
+    if (pivot != KC_PIVOT_ZERO && pivot != KC_PIVOT_SHIFT) return KC_EINVAL;
+    if (pivot == KC_PIVOT_SHIFT && !(tau > 0.0 && std::isfinite(tau))) {
+        kc::set_error("kc_factorize_solve: KC_PIVOT_SHIFT needs a finite tau > 0");
+        return KC_EINVAL;
+    }
+    if (scratch_bytes < solve_scratch_bytes(f, nrhs) || reinterpret_cast<uintptr_t>(scratch_dev) % 256) {
+        kc::set_error("kc_factorize_solve: scratch must be 256-byte aligned and hold kc_solve_bytes bytes");
+        return KC_EWORKSPACE;
+    }
+    if (!f->aux) {  // the second stream, default priority, on the current device
+        KC_HIP(hipStreamCreateWithFlags(&f->aux, hipStreamNonBlocking));
+        if (hipEventCreateWithFlags(&f->aux_ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(f->aux);
+            f->aux = nullptr;
+            kc::set_error("kc_factorize_solve: hipEventCreateWithFlags failed");
+            return KC_EHIP;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    zero_u64<<<1, 64, 0, s>>>(f->counters, kNumCounters);
+    KC_LAUNCH_CHECK();
+    gather_points<<<grid_for(f->n * f->d, kBlock), kBlock, 0, s>>>(x_dev, f->perm, f->n, f->d, f->xh);
+    KC_LAUNCH_CHECK();
+    double* y = static_cast<double*>(scratch_dev);
+    double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
+                                                align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
+    const double ell = kernel.lengthscale;
+    const kc_status st =
+        f->prec == KC_FP64
+            ? factorize_solve_typed<double>(f, tn, ell, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s)
+            : factorize_solve_typed<float>(f, tn, ell, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s);
+    if (st != KC_OK) return st;
+    f->factorized = true;
+    f->counted = false;
+    f->last = s;
+    return KC_OK;
+}
+
 kc_status kc_factor_stats(kc_factor* f, kc_factor_stats_t* st) {
     if (!f || !st) return KC_EINVAL;
     unsigned long long c[kNumCounters];
@@ -1657,7 +1769,12 @@ kc_status kc_factor_export_L(const kc_factor* f, double* vals) {
     return KC_OK;
 }
 
-void kc_factor_destroy(kc_factor* f) { delete f; }
+void kc_factor_destroy(kc_factor* f) {
+    if (!f) return;
+    if (f->aux_ev) (void)hipEventDestroy(f->aux_ev);
+    if (f->aux) (void)hipStreamDestroy(f->aux);
+    delete f;
+}
 
 kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double ell, const double* ell_dev,
                          kc_pivot pivot, double tau, int32_t reps, void* stream, int32_t* chosen_wpb) {
@@ -1680,6 +1797,9 @@ kc_status kc_factor_tune(kc_factor* f, const double* x_dev, double nu, double el
     for (int wpb : {1, 2, 4}) {
         if (factor_lds(f, vt) > kMaxLdsBytes) continue;
         for (int64_t pm : kGroupings) for (int32_t order : {KC_ORDER_SPATIAL, KC_ORDER_LONGEST}) {
+            // no level exceeds what the device holds at once: both orders share one array
+            if (order == KC_ORDER_LONGEST && f->bunits[KC_ORDER_LONGEST][0] == f->bunits[KC_ORDER_SPATIAL][0])
+                continue;
             f->wpb = wpb;
             f->persist_max = pm;
             f->order = order;

@@ -164,6 +164,34 @@ def test_solve_matches_oracle(K, nrhs):
     assert np.array_equal(x, ref)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("nrhs,persist_max", [(1, 0), (8, 0), (11, 0), (8, 16), (3, 2**63 - 1)])
+def test_factorize_solve_overlapped_bitwise(K, prec, nrhs, persist_max):
+    """The fused call (forward sweep on a second stream, overlapped with the factorization, per level
+    or per persistent run of levels) gives bitwise the factor and solution of factorize then solve,
+    on two calls in a row; in FP64 both equal the oracle."""
+    print(f"[gpu] factorize_solve prec={prec} nrhs={nrhs} persist_max={persist_max}", flush=True)
+    w = W.small_uniform_2d()
+    pivot, tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
+    plan = K.analyze(w.points, w.rho)
+    xd = dev(w.points)
+    ref_f = K.Factor(plan, prec)
+    f = K.Factor(plan, prec)
+    f.set_schedule(f.schedule()[0], persist_max)
+    for seed in (41, 42):
+        b = W.gaussian_rhs(plan.n, nrhs, seed)
+        bd = dev(b if nrhs > 1 else b[:, 0])
+        ref_f.factorize(xd, w.nu, w.lengthscale, pivot, tau)
+        ref_x = ref_f.solve(bd).cpu().numpy()
+        x = f.factorize_solve(xd, bd, w.nu, w.lengthscale, pivot, tau).cpu().numpy()
+        assert np.array_equal(x, ref_x), f"seed {seed}"
+        assert np.array_equal(f.export_L(), ref_f.export_L())
+    if prec == "fp64":
+        P, th, R = oracle_factor(w.points, w.rho, "max", w.nu, w.lengthscale)
+        assert np.array_equal(f.export_L(), R.L)
+        assert np.array_equal(x, O.solve(P, R.L, b if nrhs > 1 else b[:, 0]))
+
+
 def test_tiny_and_degenerate_inputs(K):
     print("[gpu] tiny inputs", flush=True)
     for x in (np.array([[0.3, 0.7]]), W.uniform_points(2, 2, 40), np.ones((5, 3)),
