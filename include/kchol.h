@@ -199,13 +199,15 @@ kc_status kc_solve(const kc_factor *f, const double *b_dev, double *x_dev, int32
  * stream owned by the factor (created on first use, default priority; it waits
  * on an event recorded on `stream`) runs the forward sweep of those levels,
  * while `stream` goes on with the next levels; the backward sweep runs on
- * `stream` after both.  Results are bitwise those of kc_factorize + kc_solve.
- * Arguments as for those calls (update counting is not offered); single
- * problems only (KC_EINVAL for a batch plan).  All work is ordered after
- * earlier work on `stream`, and later work on `stream` is ordered after it. */
-kc_status kc_factorize_solve(kc_factor *f, const double *x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
-                             const double *b_dev, double *x_out, int32_t nrhs, void *scratch_dev, size_t scratch_bytes,
-                             void *stream);
+ * `stream` after both.  Results are bitwise those of kc_factorize (or
+ * kc_factorize_batched) + kc_solve.  Arguments as for those calls (update
+ * counting is not offered): for a batch plan pass ell_dev, one lengthscale per
+ * instance (kernel.lengthscale is then ignored), else NULL.  All work is
+ * ordered after earlier work on `stream`, and later work on `stream` is
+ * ordered after it. */
+kc_status kc_factorize_solve(kc_factor *f, const double *x_dev, kc_kernel kernel, const double *ell_dev,
+                             kc_pivot pivot, double tau, const double *b_dev, double *x_out, int32_t nrhs,
+                             void *scratch_dev, size_t scratch_bytes, void *stream);
 
 /* Synchronises the factor's last stream and reports pivot statistics. */
 kc_status kc_factor_stats(kc_factor *f, kc_factor_stats_t *stats);

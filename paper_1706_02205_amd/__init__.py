@@ -257,10 +257,10 @@ class Factor:
                                         C.c_void_p(out.data_ptr()), _stream_ptr(stream)), "kc_theta")
         return out
 
-    def factorize_solve(self, x_dev, b_dev, nu: float, lengthscale: float, pivot: str = "zero", tau: float = 0.0,
-                        out=None, stream=None):
-        """factorize() then solve() in one call, the forward sweep overlapped with the factorization on a
-        second stream; bitwise the same result.  Returns x."""
+    def factorize_solve(self, x_dev, b_dev, nu: float, lengthscale: float = 0.0, pivot: str = "zero",
+                        tau: float = 0.0, out=None, stream=None, ell_dev=None):
+        """factorize() (or factorize_batched() with ell_dev) then solve() in one call, the forward sweep
+        overlapped with the factorization on a second stream; bitwise the same result.  Returns x."""
         import torch
         self._check_points(x_dev)
         if b_dev.dtype != torch.float64 or not b_dev.is_cuda or not b_dev.is_contiguous():
@@ -275,6 +275,7 @@ class Factor:
         if self._scratch is None or self._scratch.numel() < need:
             self._scratch = torch.empty(need, dtype=torch.uint8, device=b_dev.device)
         _lib.check(_lib.load().kc_factorize_solve(self._h, C.c_void_p(x_dev.data_ptr()), _lib.kc_kernel(nu, lengthscale),
+                                                  C.c_void_p(ell_dev.data_ptr()) if ell_dev is not None else None,
                                                   _PIVOTS[pivot], float(tau), C.c_void_p(b_dev.data_ptr()),
                                                   C.c_void_p(x.data_ptr()), nrhs, C.c_void_p(self._scratch.data_ptr()),
                                                   self._scratch.numel(), _stream_ptr(stream)), "kc_factorize_solve")

@@ -79,7 +79,7 @@ def load():
         "kc_theta": (C.c_int, [vp, vp, kc_kernel, vp, vp]),
         "kc_solve_bytes": (C.c_int, [vp, i32, P(sz)]),
         "kc_solve": (C.c_int, [vp, vp, vp, i32, vp, sz, vp]),
-        "kc_factorize_solve": (C.c_int, [vp, vp, kc_kernel, C.c_int, f64, vp, vp, i32, vp, sz, vp]),
+        "kc_factorize_solve": (C.c_int, [vp, vp, kc_kernel, vp, C.c_int, f64, vp, vp, i32, vp, sz, vp]),
         "kc_factor_stats": (C.c_int, [vp, P(kc_factor_stats_t)]),
         "kc_factor_export_L": (C.c_int, [vp, vp]),
         "kc_factor_destroy": (None, [vp]),

@@ -1163,8 +1163,8 @@ kc_status solve_typed(const kc_factor* f, const double* b, double* x, int nrhs, 
 // writes them, so the two streams never touch the same data out of order.  The
 // backward sweep needs the whole factor and runs on s after both.
 template <typename VT>
-kc_status factorize_solve_typed(kc_factor* f, int tn, double ell, int pol, double tau, const double* b, double* x,
-                                int nrhs, double* y, double* partial, hipStream_t s) {
+kc_status factorize_solve_typed(kc_factor* f, int tn, double ell, const double* ells, int pol, double tau,
+                                const double* b, double* x, int nrhs, double* y, double* partial, hipStream_t s) {
     hipStream_t aux = f->aux;
     hipEvent_t ev = f->aux_ev;
     auto after = [&](int l0, int l1) -> kc_status {
@@ -1175,7 +1175,7 @@ kc_status factorize_solve_typed(kc_factor* f, int tn, double ell, int pol, doubl
             return fwd_levels<VT, NR>(f, b, nrhs, r0, y, size_t(l0), size_t(l1), aux);
         });
     };
-    kc_status st = launch_levels<VT>(f, tn, false, ell, nullptr, pol, tau, s, after);
+    kc_status st = launch_levels<VT>(f, tn, false, ell, ells, pol, tau, s, after);
     // whatever was enqueued on aux must finish before s goes on, also after an error
     KC_HIP(hipEventRecord(ev, aux));
     KC_HIP(hipStreamWaitEvent(s, ev, 0));
@@ -1681,12 +1681,12 @@ kc_status kc_solve(const kc_factor* f, const double* b_dev, double* x_dev, int32
     return st;
 }
 
-kc_status kc_factorize_solve(kc_factor* f, const double* x_dev, kc_kernel kernel, kc_pivot pivot, double tau,
-                             const double* b_dev, double* x_out, int32_t nrhs, void* scratch_dev, size_t scratch_bytes,
-                             void* stream) {
+kc_status kc_factorize_solve(kc_factor* f, const double* x_dev, kc_kernel kernel, const double* ell_dev,
+                             kc_pivot pivot, double tau, const double* b_dev, double* x_out, int32_t nrhs,
+                             void* scratch_dev, size_t scratch_bytes, void* stream) {
     if (!f || !x_dev || !b_dev || !x_out || !scratch_dev || nrhs < 1) return KC_EINVAL;
-    if (f->ninst > 1) {
-        kc::set_error("kc_factorize_solve: the plan holds a batch; use kc_factorize_batched and kc_solve");
+    if ((f->ninst > 1) != (ell_dev != nullptr)) {
+        kc::set_error("kc_factorize_solve: pass ell_dev exactly for batch plans");
         return KC_EINVAL;
     }
     if (b_dev == x_out) {
@@ -1694,7 +1694,7 @@ kc_status kc_factorize_solve(kc_factor* f, const double* x_dev, kc_kernel kernel
         return KC_EINVAL;
     }
     const int tn = twonu_of(kernel.nu);
-    if (!tn || !(kernel.lengthscale > 0.0) || !std::isfinite(kernel.lengthscale)) {
+    if (!tn || (!ell_dev && (!(kernel.lengthscale > 0.0) || !std::isfinite(kernel.lengthscale)))) {
         kc::set_error("kc_factorize_solve: nu must be 0.5, 1.5 or 2.5 and the lengthscale finite and positive");
         return KC_EINVAL;
     }
@@ -1724,11 +1724,11 @@ kc_status kc_factorize_solve(kc_factor* f, const double* x_dev, kc_kernel kernel
     double* y = static_cast<double*>(scratch_dev);
     double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
                                                 align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
-    const double ell = kernel.lengthscale;
+    const double ell = ell_dev ? 0.0 : kernel.lengthscale;
     const kc_status st =
         f->prec == KC_FP64
-            ? factorize_solve_typed<double>(f, tn, ell, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s)
-            : factorize_solve_typed<float>(f, tn, ell, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s);
+            ? factorize_solve_typed<double>(f, tn, ell, ell_dev, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s)
+            : factorize_solve_typed<float>(f, tn, ell, ell_dev, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s);
     if (st != KC_OK) return st;
     f->factorized = true;
     f->counted = false;

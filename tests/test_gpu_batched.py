@@ -82,6 +82,22 @@ def test_graph_replays_match_eager(K, batch):
         assert np.array_equal(f.solve(bd).cpu().numpy(), eager)
 
 
+def test_fused_factorize_solve_on_a_batch(K, batch):
+    """The fused call with one lengthscale per instance gives bitwise the factor and solution of
+    factorize_batched then solve; a plan/argument mismatch is rejected."""
+    print("[gpu] batched factorize_solve", flush=True)
+    xs, ells, ref, b = batch
+    plan, f, xd, ed = run_batch(K, xs, ells)
+    bd = dev(b)
+    base_L = f.export_L()
+    base_x = f.solve(bd).cpu().numpy()
+    g = K.Factor(plan, "fp64")
+    x = g.factorize_solve(xd, bd, 1.5, ell_dev=ed).cpu().numpy()
+    assert np.array_equal(x, base_x) and np.array_equal(g.export_L(), base_L)
+    with pytest.raises(K.KCholError):
+        g.factorize_solve(xd, bd, 1.5, 0.2)  # a batch needs ell_dev
+
+
 def test_tuner_choice_does_not_change_results(K, batch):
     print("[gpu] autotuner", flush=True)
     xs, ells, ref, b = batch
