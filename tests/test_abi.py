@@ -53,3 +53,9 @@ def test_invalid_arguments_are_rejected():
     h = C.c_void_p()
     assert L.kc_analyze(C.c_void_p(x.ctypes.data), 10, 2, 2.0, 7, 0, C.byref(h)) == _lib.KC_EINVAL
     assert L.kc_analyze(None, 10, 2, 2.0, 0, 0, C.byref(h)) == _lib.KC_EINVAL
+    # factor-level calls reject a missing factor before touching a device
+    w, pm, o = C.c_int32(), C.c_int64(), C.c_int()
+    assert L.kc_factor_set_schedule(None, 1, 0, _lib.KC_ORDER_SPATIAL) == _lib.KC_EINVAL
+    assert L.kc_factor_schedule(None, C.byref(w), C.byref(pm), C.byref(o)) == _lib.KC_EINVAL
+    assert L.kc_factorize_solve(None, None, _lib.kc_kernel(0.5, 0.1), None, _lib.KC_PIVOT_ZERO, 0.0, None, None, 1,
+                                None, 0, None) == _lib.KC_EINVAL
