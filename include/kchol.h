@@ -64,7 +64,8 @@ typedef enum { KC_PIVOT_ZERO = 0, KC_PIVOT_SHIFT = 1 } kc_pivot;
  * SPATIAL: the point cloud's k-d tree order, each XCD taking one contiguous
  * slice of the level (L2 locality).  LONGEST: the unit with the longest walk
  * first, so that the last, partly filled round of a level holds short units;
- * this pays when levels are one to a few chip-fulls of wavefronts. */
+ * this pays for a single large problem, whose units of one level lie far apart
+ * anyway; a batch of small problems does better with SPATIAL. */
 typedef enum { KC_ORDER_SPATIAL = 0, KC_ORDER_LONGEST = 1 } kc_unit_order;
 
 /* Matern covariance G_{l,nu}(x,y) of Section 4.4 with unit variance; nu must be
@@ -227,10 +228,11 @@ void kc_factor_destroy(kc_factor *f);
  * separately; INT64_MAX runs the whole factorization in one persistent launch.
  * `order` is the order of the units within a level.  kc_factor_create picks
  * the defaults: wpb from the mean column length, persist_max 0, and LONGEST
- * when at least half of the units lie in levels of 8 to 32 wavefronts per SIMD,
- * else SPATIAL.  Results are bitwise identical for every schedule.  KC_EINVAL
- * for wpb not in {1, 2, 4}, persist_max < 0, an unknown order, or staged rows
- * that do not fit in LDS.  Any pointer of kc_factor_schedule may be NULL. */
+ * for a single problem with a level larger than the device holds at once,
+ * else SPATIAL (a batch keeps each problem's units together).  Results are
+ * bitwise identical for every schedule.  KC_EINVAL for wpb not in {1, 2, 4},
+ * persist_max < 0, an unknown order, or staged rows that do not fit in LDS.
+ * Any pointer of kc_factor_schedule may be NULL. */
 kc_status kc_factor_set_schedule(kc_factor *f, int32_t wpb, int64_t persist_max, kc_unit_order order);
 kc_status kc_factor_schedule(const kc_factor *f, int32_t *wpb, int64_t *persist_max, kc_unit_order *order);
 

@@ -884,9 +884,9 @@ std::vector<int32_t> unit_walks(const kc::Plan& p) {
 //  - KC_ORDER_LONGEST: longest walk first (`walk` from unit_walks; a block unit
 //    takes the longest of its wavefronts).  A workgroup lasts as long as its
 //    longest lane and workgroups start in index order, so the last, partly
-//    filled round of a level then holds the short units.  This pays when a level
-//    is one to a few chip-fulls of wavefronts (10^6-point grid: 146.9 -> 138.7 ms
-//    in FP64); with many rounds per level the lost L2 locality costs more.
+//    filled round of a level then holds the short units.  This pays for a single
+//    large problem (10^6-point grid: 146.9 -> 138.7 ms in FP64); a batch of small
+//    problems loses more L2 reuse than it gains.
 // Throws std::bad_alloc.
 void block_units(const kc::Plan& p, int wpb, int order, const std::vector<int32_t>& walk, std::vector<Unit>& bu,
                  std::vector<int64_t>& off) {
@@ -934,18 +934,15 @@ bool order_matters(const kc::Plan& p, int num_cu) {
     return false;
 }
 
-// The default unit order: longest first when at least half of the work units
-// lie in levels of more than 8 and at most 32 wavefronts per SIMD (the FP64
-// kernel holds 5 per SIMD, so such a level runs as two to seven rounds, and its
-// last, partly filled round is a large share of its time).
+// The default unit order.  SPATIAL when no level exceeds what the device holds
+// at once (order cannot matter) and for batches: the units of one small problem
+// then stay together, and its rows are reused from L2 (the 512-problem batch:
+// 112.5 ms spatial, 121.0 ms longest first).  LONGEST for a single problem,
+// whose units of one level lie far apart by construction, so balance wins (the
+// jittered grid: 146.9 -> 138.7 ms at 10^6 points, 1020.8 -> 968.6 ms at 4e6).
 int32_t default_order(const kc::Plan& p, int num_cu) {
-    const int64_t slots = waves_at_8_per_simd(num_cu);
-    int64_t in = 0;
-    for (int32_t v = 0; v < p.nlevels; ++v) {
-        const int64_t c = p.unit_off[size_t(v) + 1] - p.unit_off[size_t(v)];
-        if (c > slots && c <= 4 * slots) in += c;
-    }
-    return 2 * in >= int64_t(p.units.size()) && in > 0 ? KC_ORDER_LONGEST : KC_ORDER_SPATIAL;
+    if (!order_matters(p, num_cu) || p.ninst > 1) return KC_ORDER_SPATIAL;
+    return KC_ORDER_LONGEST;
 }
 
 int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 2 + 15) / 16 * 16); }
