@@ -151,10 +151,12 @@ def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol, keep_L=False):
         n2 = float(w.n) ** 2
         refine = {"tol": pcg_tol, "seconds_to_tol": a.elapsed_time(b) / 1e3, "iterations": info.iterations,
                   "converged": info.converged, "max_rel_residual": info.max_rel_residual,
+                  "true_rel_residual": info.true_rel_residual, "restarts": info.restarts,
                   "dense_matvec_s": info.t_matvec_ms / 1e3, "precond_s": info.t_precond_ms / 1e3,
                   "dense_pairs_per_s": n2 * info.iterations / (info.t_matvec_ms / 1e3)}
     return dict(wall=wall, wall_fused=wall_fused, t_factor=t_fac, t_solve=t_sol, updates=st.updates, rank=st2.rank,
-                nonpositive=st2.nonpositive, shifted=st2.shifted, exp_hard=st2.exp_hard, t_upload=t_upload,
+                nonpositive=st2.nonpositive, shifted=st2.shifted, exp_hard=st2.exp_hard, nonfinite=st2.nonfinite,
+                t_upload=t_upload,
                 workspace_bytes=f.workspace_bytes, refine=refine, L=f.export_L() if keep_L else None,
                 schedule=dict(zip(("waves_per_block", "persist_max", "unit_order"), f.schedule())))
 
@@ -470,7 +472,7 @@ def main():
                          "avg_launch_ms": tf / launches * 1e3},
             "factor_only": {"value": nnz / tf, "unit": "S-entries/s", "ms": tf * 1e3},
             "solve_ms": ts * 1e3, "updates": r["updates"], "rank": r["rank"], "nonpositive": r["nonpositive"],
-            "shifted": r["shifted"], "exp_hard": r["exp_hard"], "upload_s": r["t_upload"],
+            "shifted": r["shifted"], "exp_hard": r["exp_hard"], "nonfinite": r["nonfinite"], "upload_s": r["t_upload"],
             "workspace_bytes": r["workspace_bytes"], "schedule": r["schedule"],
         }
         if r["refine"] is not None:
@@ -498,7 +500,7 @@ def main():
         "step_ms": head["step_ms"],
         "solve_ms": head["solve_ms"],
         "nnz": nnz, "updates": head["updates"], "rank": head["rank"], "nonpositive": head["nonpositive"],
-        "shifted": head["shifted"], "exp_hard": head["exp_hard"],
+        "shifted": head["shifted"], "exp_hard": head["exp_hard"], "nonfinite": head["nonfinite"],
         "host_analysis_s": t_analysis, "host_analysis_split_s": [info["t_order_s"], info["t_pattern_s"],
                                                                  info["t_schedule_s"]],
         "upload_s": head["upload_s"], "workspace_bytes": head["workspace_bytes"], "schedule": head["schedule"],

@@ -102,6 +102,8 @@ typedef struct {
     int64_t rank;         /* n - nonpositive */
     int64_t updates;      /* Schur updates applied (only if counting was requested, else -1) */
     int64_t exp_hard;     /* exponentials whose rounding could not be certified (expected 0) */
+    int64_t nonfinite;    /* entries of L (diagonal included) that are inf or NaN, e.g. after a
+                             KC_PIVOT_SHIFT pivot so small that a division overflows; 0 for a usable factor */
 } kc_factor_stats_t;
 
 const char *kc_status_string(kc_status s);
@@ -229,7 +231,11 @@ void kc_factor_destroy(kc_factor *f);
  * `order` is the order of the units within a level.  kc_factor_create picks
  * the defaults: wpb from the mean column length, persist_max 0, and LONGEST
  * for a single problem with a level larger than the device holds at once,
- * else SPATIAL (a batch keeps each problem's units together).  Results are
+ * else SPATIAL (a batch keeps each problem's units together).  When no level
+ * exceeds what the device holds at once, the two orders share one array (order
+ * cannot change the speed then); asking for LONGEST on such a factor builds its
+ * own array first (a device pass over the pattern and a host sort, synchronous
+ * on the stream of the factor's last call).  Results are
  * bitwise identical for every schedule.  KC_EINVAL for wpb not in {1, 2, 4},
  * persist_max < 0, an unknown order, or staged rows that do not fit in LDS.
  * Any pointer of kc_factor_schedule may be NULL. */
@@ -252,7 +258,10 @@ kc_status kc_factor_tune(kc_factor *f, const double *x_dev, double nu, double el
  * workgroup, one launch per level).  Arguments are those of
  * kc_factorize/kc_factorize_batched and kc_solve; the pointers are baked into the
  * graph and must stay valid.  Replays on a stream are ordered like any other
- * work on it. */
+ * work on it.  Creating the graph runs nothing: the factor keeps its state
+ * (kc_solve still needs a computed factor) until the first kc_graph_launch,
+ * after which kc_factor_stats and kc_factor_export_L wait for the latest
+ * replay on the stream it was launched on. */
 kc_status kc_graph_create(kc_factor *f, const double *x_dev, double nu, double ell, const double *ell_dev,
                           kc_pivot pivot, double tau, const double *b_dev, double *sol_dev, int32_t nrhs,
                           void *scratch_dev, size_t scratch_bytes, kc_graph **out);
@@ -267,11 +276,15 @@ void kc_graph_destroy(kc_graph *g);
 /* ---------------------------------------------------------------- refinement */
 
 typedef struct {
-    int32_t iterations;        /* CG iterations performed */
-    int32_t converged;         /* 1 when every right-hand side reached tol */
-    double max_rel_residual;   /* max over right-hand sides of ||r||/||b|| (recursive residual) */
-    double t_matvec_ms;        /* time in dense Theta products */
+    int32_t iterations;        /* CG iterations performed (products with the search directions) */
+    int32_t converged;         /* 1 when every right-hand side's true residual reached tol */
+    double max_rel_residual;   /* max over right-hand sides of ||r||/||b||, recursive residual */
+    double t_matvec_ms;        /* time in dense Theta products (residual checks included) */
     double t_precond_ms;       /* time in the preconditioner solves */
+    double true_rel_residual;  /* max over right-hand sides of ||b - Theta x||/||b||, recomputed with one
+                                  dense product once the recursive residual met tol (or at maxit) */
+    int32_t restarts;          /* times CG restarted from the true residual because it was above tol */
+    int32_t pad;
 } kc_pcg_info_t;
 
 /* Y = Theta X with the dense N x N Matern matrix (Section 4.4) generated on the
@@ -286,9 +299,12 @@ kc_status kc_pcg_bytes(const kc_factor *f, int32_t nrhs, size_t *bytes);
 /* Conjugate gradients on the dense system Theta x = b preconditioned by the
  * factor, M^{-1} = P^T L^{-T} L^{-1} P (the paper suggests CG with the sparse
  * factor as preconditioner, Sections 4.2-4.3).  x0 = 0; each right-hand side
- * stops when ||r||/||b|| <= tol (FP64 residuals).  b_dev, sol_dev: N x nrhs in
- * the original order; x_dev: the points the factor was computed from.  Blocks
- * the host once per iteration for the convergence test. */
+ * stops when its recursively updated ||r||/||b|| <= tol (FP64 residuals).  Then
+ * the true residual b - Theta x is computed with one more dense product; where
+ * it is still above tol, CG restarts from it (info->restarts) until it meets tol
+ * or maxit products have been spent.  b_dev, sol_dev: N x nrhs in the original
+ * order; x_dev: the points the factor was computed from.  Blocks the host once
+ * per iteration for the convergence test. */
 kc_status kc_pcg(kc_factor *f, const double *x_dev, kc_kernel kernel, const double *b_dev, double *sol_dev,
                  int32_t nrhs, double tol, int32_t maxit, void *scratch_dev, size_t scratch_bytes, void *stream,
                  kc_pcg_info_t *info);

@@ -161,6 +161,8 @@ class PcgInfo:
     max_rel_residual: float
     t_matvec_ms: float
     t_precond_ms: float
+    true_rel_residual: float
+    restarts: int
 
 
 @dataclass
@@ -170,6 +172,7 @@ class Stats:
     rank: int
     updates: int
     exp_hard: int
+    nonfinite: int
 
 
 class Factor:
@@ -317,12 +320,12 @@ class Factor:
                                       int(maxit), C.c_void_p(scratch.data_ptr()), scratch.numel(),
                                       _stream_ptr(stream), C.byref(info)), "kc_pcg")
         return sol, PcgInfo(info.iterations, bool(info.converged), info.max_rel_residual, info.t_matvec_ms,
-                            info.t_precond_ms)
+                            info.t_precond_ms, info.true_rel_residual, info.restarts)
 
     def stats(self) -> Stats:
         st = _lib.kc_factor_stats_t()
         _lib.check(_lib.load().kc_factor_stats(self._h, C.byref(st)), "kc_factor_stats")
-        return Stats(st.nonpositive, st.shifted, st.rank, st.updates, st.exp_hard)
+        return Stats(st.nonpositive, st.shifted, st.rank, st.updates, st.exp_hard, st.nonfinite)
 
     def export_L(self) -> np.ndarray:
         """L in the plan's CSC order (float64; MIXED values widened)."""

@@ -28,12 +28,13 @@ class kc_plan_info_t(C.Structure):
 
 class kc_pcg_info_t(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("max_rel_residual", C.c_double),
-                ("t_matvec_ms", C.c_double), ("t_precond_ms", C.c_double)]
+                ("t_matvec_ms", C.c_double), ("t_precond_ms", C.c_double), ("true_rel_residual", C.c_double),
+                ("restarts", C.c_int32), ("pad", C.c_int32)]
 
 
 class kc_factor_stats_t(C.Structure):
     _fields_ = [("nonpositive", C.c_int64), ("shifted", C.c_int64), ("rank", C.c_int64),
-                ("updates", C.c_int64), ("exp_hard", C.c_int64)]
+                ("updates", C.c_int64), ("exp_hard", C.c_int64), ("nonfinite", C.c_int64)]
 
 
 EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "kc_plan_export", "kc_plan_levels", "kc_plan_set_delta_limit",

@@ -41,6 +41,9 @@ struct kc_factor {
     // each unit order ([order][w], see kc_unit_order)
     kc::Unit* bunits[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int32_t order = KC_ORDER_SPATIAL;  // kc_unit_order in use
+    // the LONGEST order's own workspace regions; bunits[KC_ORDER_LONGEST] points
+    // at SPATIAL's arrays until that order is built (build_longest)
+    kc::Unit* bunits_alt[3] = {nullptr, nullptr, nullptr};
     int64_t* boff_dev[3] = {nullptr, nullptr, nullptr};
     std::vector<int64_t> boff[3];
     int32_t* fwd_rows = nullptr;

@@ -45,7 +45,7 @@ constexpr int64_t kChunk = 512;                // entries per partial dot produc
 constexpr int kAhead = 4;                      // solve sweeps: 64-entry chunks fetched at once
 constexpr int kMaxRhsPerPass = 8;
 
-enum Counter { kNonpos = 0, kShifted = 1, kUpdates = 2, kExpHard = 3, kNumCounters = 8 };
+enum Counter { kNonpos = 0, kShifted = 1, kUpdates = 2, kExpHard = 3, kNonfinite = 4, kNumCounters = 8 };
 
 // ---------------------------------------------------------------------------
 // small kernels
@@ -91,6 +91,30 @@ __global__ __launch_bounds__(kBlock) void theta_kernel(const Unit* __restrict__ 
     double r = kcdev::dist(xh + int64_t(k) * d, xh + int64_t(j) * d, d);
     theta[e] = kcdev::matern<TWONU>(r, ell, hard);
     if (hard) atomicAdd(counters + kExpHard, 1ull);
+}
+
+// The longest walk of each 64-entry work unit: over the unit's entries (k,j),
+// the prefix of row k that precedes (k,j).  One wavefront per unit.
+__global__ __launch_bounds__(kBlock) void unit_walk_kernel(const Unit* __restrict__ units, int64_t nunits,
+                                                           const int64_t* __restrict__ colptr,
+                                                           const int32_t* __restrict__ rowidx,
+                                                           const uint32_t* __restrict__ csc2csr,
+                                                           const int64_t* __restrict__ rowptr,
+                                                           int32_t* __restrict__ walk) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t u = int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    if (u >= nunits) return;
+    const int lane = threadIdx.x % kWave;
+    const int j = units[u].col;
+    const int64_t e = colptr[j] + units[u].first + lane;
+    long long w = 0;
+    if (e < colptr[j + 1]) w = (long long)csc2csr[e] - (long long)rowptr[rowidx[e]];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long o = __shfl_xor(w, off, kWave);
+        w = o > w ? o : w;
+    }
+    if (lane == 0) walk[u] = int32_t(w < INT32_MAX ? w : INT32_MAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,6 +383,7 @@ __device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, in
         }
     }
     const double ljj = zero ? 0.0 : __builtin_sqrt(piv);
+    bool bad = false;
     if (active) {
         VT out;
         if (zero) out = VT(0);
@@ -369,7 +394,11 @@ __device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, in
         Lcsc[e] = out;
         if constexpr (sizeof(VT) == 4)
             if (k == j) diag[j] = ljj;
+        bad = !__builtin_isfinite(out);
     }
+    // entries of L that came out inf or NaN (e.g. after a tiny shifted pivot): one atomic per wave
+    const unsigned long long nf = __ballot(bad);
+    if (nf && lane == 0) atomicAdd(counters + kNonfinite, (unsigned long long)__popcll(nf));
     if (first == 0 && lane == 0) {
         if (zero) atomicAdd(counters + kNonpos, 1ull);
         if (shifted) atomicAdd(counters + kShifted, 1ull);
@@ -833,15 +862,13 @@ int64_t waves_at_8_per_simd(int num_cu) { return int64_t(std::max(1, num_cu)) * 
 // threads (one thread for small plans).  fn may throw std::bad_alloc, which is
 // rethrown here.
 template <typename Fn>
-void for_levels(const kc::Plan& p, Fn fn) {
-    const int nt = p.nnz() < (int64_t(1) << 22)
-                       ? 1
-                       : int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+void for_levels(int32_t nlevels, bool parallel, Fn fn) {
+    const int nt = parallel ? int(std::min(16u, std::max(1u, std::thread::hardware_concurrency()))) : 1;
     std::atomic<int32_t> next{0};
     std::atomic<bool> failed{false};
     auto work = [&]() {
         try {
-            for (int32_t v; !failed.load() && (v = next.fetch_add(1)) < p.nlevels;) fn(v);
+            for (int32_t v; !failed.load() && (v = next.fetch_add(1)) < nlevels;) fn(v);
         } catch (const std::bad_alloc&) {
             failed = true;
         }
@@ -860,9 +887,11 @@ void for_levels(const kc::Plan& p, Fn fn) {
 // The longest walk of each work unit (64 entries of a column): the longest
 // prefix of row k before (k,j) over its entries.  A wavefront lasts about as
 // long as its longest lane.  Throws std::bad_alloc.
+bool big_plan(const kc::Plan& p) { return p.nnz() >= (int64_t(1) << 22); }
+
 std::vector<int32_t> unit_walks(const kc::Plan& p) {
     std::vector<int32_t> walk(p.units.size());
-    for_levels(p, [&](int32_t v) {
+    for_levels(p.nlevels, big_plan(p), [&](int32_t v) {
         for (int64_t u = p.unit_off[size_t(v)]; u < p.unit_off[size_t(v) + 1]; ++u) {
             const Unit un = p.units[size_t(u)];
             const int64_t e0 = p.colptr[size_t(un.col)] + un.first;
@@ -888,15 +917,16 @@ std::vector<int32_t> unit_walks(const kc::Plan& p) {
 //    large problem (10^6-point grid: 146.9 -> 138.7 ms in FP64); a batch of small
 //    problems loses more L2 reuse than it gains.
 // Throws std::bad_alloc.
-void block_units(const kc::Plan& p, int wpb, int order, const std::vector<int32_t>& walk, std::vector<Unit>& bu,
-                 std::vector<int64_t>& off) {
+void block_units(const std::vector<Unit>& units, const std::vector<int64_t>& unit_off, bool parallel, int wpb,
+                 int order, const std::vector<int32_t>& walk, std::vector<Unit>& bu, std::vector<int64_t>& off) {
     const int per = kWave * wpb;
+    const int32_t nlevels = int32_t(unit_off.size()) - 1;
     std::vector<int32_t> key;
     bu.clear();
-    off.assign(size_t(p.nlevels) + 1, 0);
-    for (int32_t v = 0; v < p.nlevels; ++v) {
-        for (int64_t u = p.unit_off[size_t(v)]; u < p.unit_off[size_t(v) + 1]; ++u) {
-            const Unit un = p.units[size_t(u)];
+    off.assign(size_t(nlevels) + 1, 0);
+    for (int32_t v = 0; v < nlevels; ++v) {
+        for (int64_t u = unit_off[size_t(v)]; u < unit_off[size_t(v) + 1]; ++u) {
+            const Unit un = units[size_t(u)];
             const int32_t w = order == KC_ORDER_LONGEST ? walk[size_t(u)] : 0;
             if (un.first % per == 0) {
                 bu.push_back(un);
@@ -907,7 +937,7 @@ void block_units(const kc::Plan& p, int wpb, int order, const std::vector<int32_
         }
         off[size_t(v) + 1] = int64_t(bu.size());
     }
-    for_levels(p, [&](int32_t v) {
+    for_levels(nlevels, parallel, [&](int32_t v) {
         const int64_t b0 = off[size_t(v)], b1 = off[size_t(v) + 1], nb = b1 - b0;
         std::vector<std::pair<int32_t, Unit>> lvl;
         lvl.reserve(size_t(nb));
@@ -943,6 +973,52 @@ bool order_matters(const kc::Plan& p, int num_cu) {
 int32_t default_order(const kc::Plan& p, int num_cu) {
     if (!order_matters(p, num_cu) || p.ninst > 1) return KC_ORDER_SPATIAL;
     return KC_ORDER_LONGEST;
+}
+
+// The LONGEST unit order of a factor created with both orders sharing SPATIAL's
+// arrays (no level exceeds what the device holds at once, so the order cannot
+// change the speed): the unit walks from a device pass over the pattern, sorted
+// on the host as block_units does, into the LONGEST region of the workspace.
+// Synchronous on s.
+kc_status build_longest(kc_factor* f, hipStream_t s) {
+    if (f->bunits[KC_ORDER_LONGEST][0] != f->bunits[KC_ORDER_SPATIAL][0]) return KC_OK;  // already built
+    const int64_t nu = f->nunits;
+    std::vector<Unit> units;
+    std::vector<int32_t> walk;
+    try {
+        units.resize(size_t(nu));
+        walk.resize(size_t(nu));
+    } catch (const std::bad_alloc&) {
+        return KC_ENOMEM;
+    }
+    if (nu > 0) {
+        // the LONGEST region for one wavefront per block holds nunits units: room for the walks
+        int32_t* wdev = reinterpret_cast<int32_t*>(f->bunits_alt[0]);
+        unit_walk_kernel<<<grid_for(nu, kWavesPerBlock), kBlock, 0, s>>>(f->units, nu, f->colptr, f->rowidx,
+                                                                         f->csc2csr, f->rowptr, wdev);
+        KC_LAUNCH_CHECK();
+        KC_HIP(hipMemcpyAsync(walk.data(), wdev, size_t(nu) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        KC_HIP(hipMemcpyAsync(units.data(), f->units, size_t(nu) * sizeof(Unit), hipMemcpyDeviceToHost, s));
+        KC_HIP(hipStreamSynchronize(s));
+    }
+    for (int w = 0; w < 3; ++w) {
+        std::vector<Unit> bu;
+        std::vector<int64_t> off;
+        try {
+            block_units(units, f->unit_off, nu >= (int64_t(1) << 16), 1 << w, KC_ORDER_LONGEST, walk, bu, off);
+        } catch (const std::bad_alloc&) {
+            return KC_ENOMEM;
+        }
+        if (off != f->boff[w]) {
+            kc::set_error("build_longest: block units differ from the factor's level offsets");
+            return KC_ESTATE;
+        }
+        if (!bu.empty())
+            KC_HIP(hipMemcpyAsync(f->bunits_alt[w], bu.data(), bu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
+        KC_HIP(hipStreamSynchronize(s));  // bu is a local buffer
+    }
+    for (int w = 0; w < 3; ++w) f->bunits[KC_ORDER_LONGEST][w] = f->bunits_alt[w];
+    return KC_OK;
 }
 
 int32_t lds_cap(const kc::Plan& p) { return int32_t((p.max_row + 2 + 15) / 16 * 16); }
@@ -1500,6 +1576,7 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     f->unit_off_dev = reinterpret_cast<int64_t*>(base + o.unit_off);
     for (int w = 0; w < 3; ++w) {
         for (int r = 0; r < 2; ++r) f->bunits[r][w] = reinterpret_cast<Unit*>(base + o.bunits[r][w]);
+        f->bunits_alt[w] = f->bunits[KC_ORDER_LONGEST][w];
         f->boff_dev[w] = reinterpret_cast<int64_t*>(base + o.boff[w]);
     }
     f->fwd_rows = reinterpret_cast<int32_t*>(base + o.fwd);
@@ -1545,7 +1622,7 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
         for (int r = 0; r < (both ? 2 : 1); ++r) {
             std::vector<Unit> bu;
             try {
-                block_units(p, 1 << w, r, walk, bu, f->boff[w]);
+                block_units(p.units, p.unit_off, big_plan(p), 1 << w, r, walk, bu, f->boff[w]);
             } catch (const std::bad_alloc&) {
                 return KC_ENOMEM;
             }
@@ -1743,6 +1820,7 @@ kc_status kc_factor_stats(kc_factor* f, kc_factor_stats_t* st) {
     st->rank = f->n - int64_t(c[kNonpos]);
     st->updates = f->counted ? int64_t(c[kUpdates]) : -1;
     st->exp_hard = int64_t(c[kExpHard]);
+    st->nonfinite = int64_t(c[kNonfinite]);
     return KC_OK;
 }
 
@@ -1844,6 +1922,10 @@ kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max,
         kc::set_error("kc_factor_set_schedule: the staged row does not fit in LDS");
         return KC_EINVAL;
     }
+    if (order == KC_ORDER_LONGEST) {
+        const kc_status st = build_longest(f, f->last);
+        if (st != KC_OK) return st;
+    }
     f->wpb = wpb;
     f->persist_max = persist_max;
     f->order = order;
@@ -1861,6 +1943,7 @@ kc_status kc_factor_schedule(const kc_factor* f, int32_t* wpb, int64_t* persist_
 struct kc_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    kc_factor* f = nullptr;  // the factor whose factorize + solve the graph replays
     int32_t persistent = 0;  // the factorization was recorded with persistent launches
     ~kc_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1909,11 +1992,19 @@ kc_status kc_graph_create(kc_factor* f, const double* x_dev, double nu, double e
     // Graphs record one launch per level: cooperative launches are not recorded
     // (the grid barrier of a persistent launch needs the runtime's cooperative
     // launch path at every replay).  The factor's own schedule is kept for eager use.
+    // Capturing records the launches without running them: the factor's state
+    // (its last stream -- the capture stream is destroyed below -- and whether L
+    // has been computed) stays what it was until a replay runs.
     const int64_t pm = f->persist_max;
+    hipStream_t const last = f->last;
+    const bool factorized = f->factorized, counted = f->counted;
     f->persist_max = 0;
     hipError_t e = hipSuccess;
     kc_status st = capture(e);
     f->persist_max = pm;
+    f->last = last;
+    f->factorized = factorized;
+    f->counted = counted;
     const bool persistent_recorded = false;
     if (e != hipSuccess) {
         kc::set_error(std::string("kc_graph_create: capture failed: ") + hipGetErrorString(e));
@@ -1922,7 +2013,7 @@ kc_status kc_graph_create(kc_factor* f, const double* x_dev, double nu, double e
     if (st != KC_OK) return st;
     KC_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     g->persistent = persistent_recorded ? 1 : 0;
-    f->factorized = true;
+    g->f = f;
     *out = g.release();
     return KC_OK;
 }
@@ -1941,6 +2032,10 @@ kc_status kc_graph_info(const kc_graph* g, int64_t* nodes, int32_t* persistent) 
 kc_status kc_graph_launch(kc_graph* g, void* stream) {
     if (!g) return KC_EINVAL;
     KC_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    // the replay computes L on `stream`: stats and export wait for it there
+    g->f->last = static_cast<hipStream_t>(stream);
+    g->f->factorized = true;
+    g->f->counted = false;
     return KC_OK;
 }
 

@@ -237,6 +237,13 @@ __global__ void fill_zero(double* __restrict__ a, int64_t m) {
     if (i < m) a[i] = 0.0;
 }
 
+// r = b - q
+__global__ void sub_vec(const double* __restrict__ b, const double* __restrict__ q, double* __restrict__ r,
+                        int64_t m) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < m) r[i] = b[i] - q[i];
+}
+
 __global__ void copy_vec(const double* __restrict__ a, double* __restrict__ b, int64_t m) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < m) b[i] = a[i];
@@ -452,8 +459,33 @@ kc_status kc_pcg(kc_factor* f, const double* x_dev, kc_kernel kernel, const doub
     copy_vec<<<gb, 256, 0, s>>>(z, p, m);
     PCG_HIP(launch_dot(r, z, f->n, nrhs, partial, rz, s));
 
-    int it = 0;
-    double worst = 0.0;
+    // True residual r = b - Theta x (one dense product), which replaces the
+    // recursively updated one; returns max over right-hand sides of ||r||/||b||
+    // and marks the right-hand sides still above tol as active.
+    std::vector<double> hrel(nrhs, 0.0);
+    auto true_residual = [&](double& out) -> hipError_t {
+        hipError_t e;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+        if ((e = launch_matvec(tn, x_dev, f->n, f->d, kernel.lengthscale, sol_dev, nrhs, q, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+        sub_vec<<<gb, 256, 0, s>>>(b_dev, q, r, m);
+        if ((e = launch_dot(r, r, f->n, nrhs, partial, rr, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(hr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+        t_mv += ms;
+        out = 0.0;
+        for (int k = 0; k < nrhs; ++k) {
+            hrel[k] = hb[k] > 0.0 ? std::sqrt(hr[k] / hb[k]) : 0.0;
+            out = std::max(out, hrel[k]);
+            hact[k] = hrel[k] > tol ? 1 : 0;
+        }
+        return hipSuccess;
+    };
+
+    int it = 0, restarts = 0;
+    double worst = 0.0, true_worst = -1.0;
     bool done = false;
     for (it = 1; it <= maxit; ++it) {
         PCG_HIP(hipEventRecord(e0, s));
@@ -476,8 +508,26 @@ kc_status kc_pcg(kc_factor* f, const double* x_dev, kc_kernel kernel, const doub
             any = any || hact[k];
         }
         if (!any) {
-            done = true;
-            break;
+            // the recursive residual has converged: confirm with the true one, and
+            // where rounding let the two drift apart, restart CG from the current x
+            PCG_HIP(true_residual(true_worst));
+            if (true_worst <= tol || it == maxit) {
+                done = true_worst <= tol;
+                break;
+            }
+            ++restarts;
+            PCG_HIP(hipMemcpyAsync(act, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+            PCG_HIP(hipEventRecord(e0, s));
+            st = kc_solve(f, r, z, nrhs, solve_scratch, sb, stream);
+            if (st != KC_OK) return st;
+            PCG_HIP(hipEventRecord(e1, s));
+            copy_vec<<<gb, 256, 0, s>>>(z, p, m);
+            PCG_HIP(launch_dot(r, z, f->n, nrhs, partial, rz, s));
+            PCG_HIP(hipStreamSynchronize(s));
+            PCG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            t_pc += ms;
+            true_worst = -1.0;
+            continue;
         }
         PCG_HIP(hipMemcpyAsync(act, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
         PCG_HIP(hipEventRecord(e0, s));
@@ -492,9 +542,12 @@ kc_status kc_pcg(kc_factor* f, const double* x_dev, kc_kernel kernel, const doub
         t_pc += ms;
     }
     PCG_HIP(hipStreamSynchronize(s));
-    info->iterations = done ? it : maxit;
+    if (true_worst < 0.0) PCG_HIP(true_residual(true_worst));  // stopped at maxit
+    info->iterations = std::min(it, maxit);
     info->converged = done ? 1 : 0;
     info->max_rel_residual = worst;
+    info->true_rel_residual = true_worst;
+    info->restarts = restarts;
     info->t_matvec_ms = t_mv;
     info->t_precond_ms = t_pc;
     return KC_OK;

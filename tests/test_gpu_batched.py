@@ -161,6 +161,33 @@ def test_single_problem_graph(K):
         assert np.array_equal(out.cpu().numpy(), eager)
 
 
+def test_graph_state_without_device_synchronize(K):
+    """Capturing records and runs nothing: a fresh factor stays uncomputed (kc_solve refuses it)
+    and stats/export wait for nothing on the destroyed capture stream.  After a replay, stats and
+    export_L wait for that replay on its own stream -- no device-wide synchronize in between --
+    and see the replay's L."""
+    print("[gpu] graph state after capture and replay", flush=True)
+    import torch
+    w = W.small_uniform_2d()
+    plan = K.analyze(w.points, w.rho)
+    xd, bd = dev(w.points), dev(w.rhs())
+    ref = K.Factor(plan, "fp64")
+    ref.factorize(xd, w.nu, w.lengthscale)
+    ref_L, ref_x, ref_st = ref.export_L(), ref.solve(bd).cpu().numpy(), ref.stats()
+    f = K.Factor(plan, "fp64")
+    g = f.capture(xd, bd, w.nu, w.lengthscale)
+    with pytest.raises(K.KCholError, match="call out of order"):
+        f.solve(bd)  # nothing has computed L yet
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = g.launch(stream=s)
+    st = f.stats()  # waits on s
+    assert st.nonpositive == ref_st.nonpositive and st.nonfinite == 0
+    assert np.array_equal(f.export_L(), ref_L)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref_x)
+
+
 def test_batched_mixed_error(K, batch):
     print("[gpu] batched mixed", flush=True)
     xs, ells, ref, b = batch

@@ -114,11 +114,24 @@ def test_pcg_true_residual_on_sampled_rows(big):
     f = K.Factor(plan, "mixed")
     xd = torch.from_numpy(w.points).to("cuda")
     f.factorize(xd, w.nu, w.lengthscale, "shift", 1e-6)
-    sol, info = f.pcg(xd, torch.from_numpy(big["b"]).to("cuda"), w.nu, w.lengthscale, tol=1e-10)
-    sol = sol.cpu().numpy()
-    assert info.converged and info.max_rel_residual <= 1e-10
+    bd = torch.from_numpy(big["b"]).to("cuda")
+    sol_d, info = f.pcg(xd, bd, w.nu, w.lengthscale, tol=1e-10)
+    sol = sol_d.cpu().numpy()
+    # the library's own true residual ||b - Theta x|| / ||b|| meets the target
+    assert info.converged and info.max_rel_residual <= 1e-10 and info.true_rel_residual <= 1e-10
+    # the library's dense product against the oracle's on sampled rows: within 1e-12 of sum |Theta||x|
     rows = np.random.default_rng(2).integers(0, w.n, 200)
-    r = big["b"][rows] - O.dense_matvec_rows(w.points, sol, w.nu, w.lengthscale, rows)
+    prod = K.dense_matvec(xd, sol_d, w.nu, w.lengthscale).cpu().numpy()[rows]
+    exact = O.dense_matvec_rows(w.points, sol, w.nu, w.lengthscale, rows)
+    scale = O.dense_matvec_rows(w.points, np.abs(sol), w.nu, w.lengthscale, rows)
+    prod_err = np.max(np.abs(prod - exact) / scale)
+    # the residual with the oracle's (exact-exp) product on those rows, as an RMS estimate of the whole
+    r = big["b"][rows] - exact
     rms_rel = np.sqrt((r ** 2).mean(axis=0) * w.n) / np.linalg.norm(big["b"], axis=0)
-    print(f"[gpu] full size: {info.iterations} CG iterations, sampled true residual {rms_rel.max():.2e}", flush=True)
-    assert np.all(rms_rel < 3e-10)
+    print(f"[gpu] full size: {info.iterations} CG iterations, {info.restarts} restarts, true residual "
+          f"{info.true_rel_residual:.2e} (library product), sampled {rms_rel.max():.2e} (oracle product); "
+          f"product error {prod_err:.1e} of |Theta||x|", flush=True)
+    assert prod_err < 1e-12
+    # the two residuals differ by the product error, (Theta_lib - Theta) x, at most prod_err * |Theta||x|
+    slack = prod_err * np.sqrt((scale ** 2).mean(axis=0) * w.n) / np.linalg.norm(big["b"], axis=0)
+    assert np.all(rms_rel < 1e-10 + slack + 2e-11)  # 2e-11: the RMS estimate from 200 rows

@@ -60,8 +60,13 @@ def test_pcg_reaches_tolerance(K, prec):
     sol, info = f.pcg(xd, dev(b), w.nu, w.lengthscale, tol=1e-10)
     sol = sol.cpu().numpy()
     assert info.converged and info.max_rel_residual <= 1e-10
+    assert info.true_rel_residual <= 1e-10  # recomputed with the library's dense product
     true = np.linalg.norm(b - O.dense_matvec(w.points, sol, w.nu, w.lengthscale), axis=0) / np.linalg.norm(b, axis=0)
-    print(f"[gpu] pcg {prec}: {info.iterations} iterations (oracle fp64: {it_ref}), true residual {true.max():.2e}",
+    print(f"[gpu] pcg {prec}: {info.iterations} iterations (oracle fp64: {it_ref}), {info.restarts} restarts, "
+          f"true residual {info.true_rel_residual:.2e} (library product) {true.max():.2e} (oracle product)",
           flush=True)
+    # the oracle's product differs from the library's by the latter's rounding (<= 1e-12 of
+    # sum |Theta||x| per row, test_dense_matvec_matches_oracle); here that moves the residual
+    # by well under half the target
     assert np.all(true <= 1.5e-10)
-    assert abs(info.iterations - it_ref) <= 1
+    assert abs(info.iterations - it_ref) <= 1 + 2 * info.restarts

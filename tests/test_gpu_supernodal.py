@@ -49,6 +49,33 @@ def test_supernodal_factor_and_solve_bitwise(K, nu, d, pivot):
         assert np.array_equal(f.solve(dev(b)).cpu().numpy(), O.solve(Pn, R.L, b))
 
 
+def test_nonfinite_factor_is_counted_and_matches_oracle(K):
+    """Matern-5/2 in 3-D on the supernodal pattern with SHIFT and tau = 1e-9: a shifted pivot
+    of 1e-9 makes later divisions overflow, so L holds inf and NaN entries.  The count of
+    non-finite entries is reported (kc_factor_stats.nonfinite) and equals the oracle's; the
+    non-finite entries sit at the same positions (NaN where the oracle has NaN, inf of the same
+    sign), and the finite ones are bitwise equal."""
+    print("[gpu] non-finite factor nu=2.5 d=3 shift tau=1e-9", flush=True)
+    x = W.uniform_points(2000, 3, 31)
+    Pn, sptr = O.supernodal_pattern(x, 3.0)
+    R = O.ichol(Pn, O.theta_on_pattern(Pn, 2.5, 0.2), O.PIVOT_SHIFT, 1e-9)
+    bad = ~np.isfinite(R.L)
+    assert bad.sum() > 100  # the case exercises non-finite entries
+    plan = K.analyze_supernodal(x, 3.0)
+    f = K.Factor(plan, "fp64")
+    f.factorize(dev(x), 2.5, 0.2, "shift", 1e-9, count_updates=True)
+    st = f.stats()
+    L = f.export_L()
+    assert st.nonfinite == int(bad.sum())
+    assert st.shifted == R.shifted and st.updates == R.updates
+    assert np.array_equal(np.isnan(L), np.isnan(R.L))
+    assert np.array_equal(L[np.isinf(R.L)], R.L[np.isinf(R.L)])
+    assert np.array_equal(L[~bad], R.L[~bad])
+    # a usable factor reports none
+    f.factorize(dev(x), 2.5, 0.2, "zero")
+    assert f.stats().nonfinite == 0
+
+
 @pytest.mark.slow
 def test_uniform3d_subsample(K):
     print("[gpu] supernodal 3-D subsample", flush=True)
