@@ -196,6 +196,20 @@ kc_status kc_solve_bytes(const kc_factor *f, int32_t nrhs, size_t *bytes);
 kc_status kc_solve(const kc_factor *f, const double *b_dev, double *x_dev, int32_t nrhs, void *scratch_dev,
                    size_t scratch_bytes, void *stream);
 
+/* kc_solve for callers that cannot allocate device memory -- code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same kernels and result as kc_solve (bitwise), but its scratch (the forward
+ * sweep's intermediate vector and the long columns' partial sums,
+ * kc_solve_bytes) lives in one fixed array of 96 MiB that the library holds on
+ * each device it runs on until the process ends; no call allocates or frees
+ * memory.  A solve needing more than 96 MiB of scratch (N * nrhs * 8 bytes
+ * plus the partial sums; e.g. 10^6 points with 8 right-hand sides fits)
+ * returns KC_EWORKSPACE before any work.  Every call on one device shares that
+ * device's array: calls that overlap on one device (on different streams, or
+ * from different threads) race and give wrong results; calls ordered on one
+ * stream are safe.  Arguments as for kc_solve. */
+kc_status kc_solve_noalloc(const kc_factor *f, const double *b_dev, double *x_dev, int32_t nrhs, void *stream);
+
 /* kc_factorize followed by kc_solve (Section 2.2 and Section 1, task (2)) in one
  * call, with the forward sweep overlapped with the factorization: after the
  * launch covering factor levels [l0, l1) is enqueued on `stream`, a second

@@ -303,6 +303,21 @@ class Factor:
                                         _stream_ptr(stream)), "kc_solve")
         return x
 
+    def solve_noalloc(self, b_dev, out, stream=None):
+        """solve() through kc_solve_noalloc: the library's fixed per-device scratch array instead of a
+        workspace, so the call allocates nothing (``out`` must be given).  Calls that overlap on one
+        device race on that array."""
+        import torch
+        for t in (b_dev, out):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("b and out must be contiguous float64 CUDA tensors")
+        if b_dev.shape[0] != self.n or out.shape != b_dev.shape:
+            raise ValueError("b must have n rows and out the shape of b")
+        nrhs = 1 if b_dev.dim() == 1 else int(b_dev.shape[1])
+        _lib.check(_lib.load().kc_solve_noalloc(self._h, C.c_void_p(b_dev.data_ptr()), C.c_void_p(out.data_ptr()),
+                                                nrhs, _stream_ptr(stream)), "kc_solve_noalloc")
+        return out
+
     def pcg(self, x_dev, b_dev, nu: float, lengthscale: float, tol: float = 1e-10, maxit: int = 200, stream=None):
         """Solve Theta x = b by CG on the dense Theta preconditioned with this factor."""
         import torch

@@ -42,7 +42,7 @@ EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "
             "kc_solve", "kc_factorize_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
             "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
             "kc_factor_tune", "kc_factor_set_schedule", "kc_factor_schedule", "kc_graph_create", "kc_graph_info", "kc_graph_launch", "kc_graph_destroy", "kc_analyze_supernodal",
-            "kc_plan_supernodes")
+            "kc_plan_supernodes", "kc_solve_noalloc")
 
 _LIB = None
 
@@ -99,6 +99,7 @@ def load():
         "kc_graph_destroy": (None, [vp]),
         "kc_analyze_supernodal": (C.c_int, [vp, i64, i32, f64, i32, P(vp)]),
         "kc_plan_supernodes": (C.c_int, [vp, vp, P(i64)]),
+        "kc_solve_noalloc": (C.c_int, [vp, vp, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -21,6 +21,7 @@
 #include <climits>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <atomic>
 #include <thread>
@@ -1748,6 +1749,80 @@ kc_status kc_solve(const kc_factor* f, const double* b_dev, double* x_dev, int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* y = static_cast<double*>(scratch_dev);
     double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
+                                                align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
+    const kc_status st = f->prec == KC_FP64 ? solve_typed<double>(f, b_dev, x_dev, nrhs, y, partial, s)
+                                            : solve_typed<float>(f, b_dev, x_dev, nrhs, y, partial, s);
+    const_cast<kc_factor*>(f)->last = s;
+    return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Scratch of kc_solve_noalloc: one array per device that loads the library,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(96) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+kc_status noalloc_scratch(void** out) {
+    int dev = 0;
+    KC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        kc::set_error("kc_solve_noalloc: device index " + std::to_string(dev) + " beyond the supported range");
+        return KC_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        KC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            kc::set_error("kc_solve_noalloc: hipGetSymbolAddress returned no address for the scratch array");
+            return KC_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return KC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+kc_status kc_solve_noalloc(const kc_factor* f, const double* b_dev, double* x_dev, int32_t nrhs, void* stream) {
+    if (!f || !b_dev || !x_dev || nrhs < 1) return KC_EINVAL;
+    if (b_dev == x_dev) {
+        kc::set_error("kc_solve_noalloc: b and x must not alias");
+        return KC_EINVAL;
+    }
+    if (!f->factorized) {
+        kc::set_error("kc_solve_noalloc: factor has not been computed");
+        return KC_ESTATE;
+    }
+    const size_t need = solve_scratch_bytes(f, nrhs);
+    if (need > kNoAllocScratchBytes) {
+        kc::set_error("kc_solve_noalloc: this solve needs " + std::to_string(need) +
+                      " bytes of scratch, beyond the library's fixed " + std::to_string(kNoAllocScratchBytes) +
+                      "; use kc_solve with caller-owned scratch");
+        return KC_EWORKSPACE;
+    }
+    void* base = nullptr;
+    const kc_status got = noalloc_scratch(&base);
+    if (got != KC_OK) return got;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* y = static_cast<double*>(base);
+    double* partial = reinterpret_cast<double*>(static_cast<char*>(base) +
                                                 align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
     const kc_status st = f->prec == KC_FP64 ? solve_typed<double>(f, b_dev, x_dev, nrhs, y, partial, s)
                                             : solve_typed<float>(f, b_dev, x_dev, nrhs, y, partial, s);
