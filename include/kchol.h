@@ -104,6 +104,8 @@ typedef struct {
     int64_t exp_hard;     /* exponentials whose rounding could not be certified (expected 0) */
     int64_t nonfinite;    /* entries of L (diagonal included) that are inf or NaN, e.g. after a
                              KC_PIVOT_SHIFT pivot so small that a division overflows; 0 for a usable factor */
+    int64_t match_errors; /* entries whose match masks disagreed with the pattern (expected 0; see
+                             kc_factor_match_build) */
 } kc_factor_stats_t;
 
 const char *kc_status_string(kc_status s);
@@ -225,6 +227,30 @@ kc_status kc_solve_noalloc(const kc_factor *f, const double *b_dev, double *x_de
 kc_status kc_factorize_solve(kc_factor *f, const double *x_dev, kc_kernel kernel, const double *ell_dev,
                              kc_pivot pivot, double tau, const double *b_dev, double *x_out, int32_t nrhs,
                              void *scratch_dev, size_t scratch_bytes, void *stream);
+
+/* Match masks: symbolic data that speeds up the factorization of this pattern.
+ * The elimination of Section 2.2 updates entry (k,j) with every parent i < j
+ * that row k and row j share, in ascending order.  Without masks each update
+ * is found by merging the column indices of row k (read from HBM) with those of
+ * row j.  With masks, two bit strings per entry record the shared parents
+ * once: one bit per entry of row k before (k,j) and one per parent of j; the
+ * factorization then reads one bit instead of a 16-bit index per entry it
+ * walks, stops at the last shared parent, and skips value lines holding none.
+ * L is bitwise the same either way (same updates, same order).
+ *
+ * kc_factor_match_bytes: device bytes the masks need -- an 8-byte word per
+ * entry of S plus about (pos + np) / 64 8-byte words per entry, pos being the
+ * entries of row k before (k,j) and np the parents of j (some 24 GB for 10^6
+ * points at rho = 4).  Counting runs on the device, synchronously on `stream`,
+ * once per factor.
+ * kc_factor_match_build: builds the masks in the caller-owned buffer buf_dev
+ * (>= kc_factor_match_bytes, 256-byte aligned), synchronously on `stream`;
+ * later factorizations of this factor use them.  The buffer must stay valid
+ * while they are attached; buf_dev = NULL detaches them (back to the index
+ * merge).  KC_EWORKSPACE for a short or misaligned buffer, KC_ERANGE if a
+ * row is too long to stage (more than about 10,000 entries). */
+kc_status kc_factor_match_bytes(kc_factor *f, void *stream, size_t *bytes);
+kc_status kc_factor_match_build(kc_factor *f, void *buf_dev, size_t bytes, void *stream);
 
 /* Synchronises the factor's last stream and reports pivot statistics. */
 kc_status kc_factor_stats(kc_factor *f, kc_factor_stats_t *stats);

@@ -173,6 +173,7 @@ class Stats:
     updates: int
     exp_hard: int
     nonfinite: int
+    match_errors: int
 
 
 class Factor:
@@ -337,10 +338,33 @@ class Factor:
         return sol, PcgInfo(info.iterations, bool(info.converged), info.max_rel_residual, info.t_matvec_ms,
                             info.t_precond_ms, info.true_rel_residual, info.restarts)
 
+    def match_bytes(self, stream=None) -> int:
+        """Device bytes the match masks of this factor's pattern need (counted on the device once)."""
+        nb = C.c_size_t()
+        _lib.check(_lib.load().kc_factor_match_bytes(self._h, _stream_ptr(stream), C.byref(nb)),
+                   "kc_factor_match_bytes")
+        return int(nb.value)
+
+    def build_matches(self, stream=None) -> int:
+        """Build the match masks (symbolic, once per pattern) in a torch-allocated buffer kept by this
+        object; later factorizations use them and give bitwise the same L.  Returns their bytes."""
+        import torch
+        need = self.match_bytes(stream)
+        self._matches = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        _lib.check(_lib.load().kc_factor_match_build(self._h, C.c_void_p(self._matches.data_ptr()),
+                                                     self._matches.numel(), _stream_ptr(stream)),
+                   "kc_factor_match_build")
+        return need
+
+    def drop_matches(self) -> None:
+        """Detach and free the match masks (back to the index merge)."""
+        _lib.check(_lib.load().kc_factor_match_build(self._h, None, 0, None), "kc_factor_match_build")
+        self._matches = None
+
     def stats(self) -> Stats:
         st = _lib.kc_factor_stats_t()
         _lib.check(_lib.load().kc_factor_stats(self._h, C.byref(st)), "kc_factor_stats")
-        return Stats(st.nonpositive, st.shifted, st.rank, st.updates, st.exp_hard, st.nonfinite)
+        return Stats(st.nonpositive, st.shifted, st.rank, st.updates, st.exp_hard, st.nonfinite, st.match_errors)
 
     def export_L(self) -> np.ndarray:
         """L in the plan's CSC order (float64; MIXED values widened)."""

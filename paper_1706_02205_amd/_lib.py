@@ -34,7 +34,8 @@ class kc_pcg_info_t(C.Structure):
 
 class kc_factor_stats_t(C.Structure):
     _fields_ = [("nonpositive", C.c_int64), ("shifted", C.c_int64), ("rank", C.c_int64),
-                ("updates", C.c_int64), ("exp_hard", C.c_int64), ("nonfinite", C.c_int64)]
+                ("updates", C.c_int64), ("exp_hard", C.c_int64), ("nonfinite", C.c_int64),
+                ("match_errors", C.c_int64)]
 
 
 EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "kc_plan_export", "kc_plan_levels", "kc_plan_set_delta_limit",
@@ -42,7 +43,7 @@ EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "
             "kc_solve", "kc_factorize_solve", "kc_factor_stats", "kc_factor_export_L", "kc_factor_destroy", "kc_device_count",
             "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
             "kc_factor_tune", "kc_factor_set_schedule", "kc_factor_schedule", "kc_graph_create", "kc_graph_info", "kc_graph_launch", "kc_graph_destroy", "kc_analyze_supernodal",
-            "kc_plan_supernodes", "kc_solve_noalloc")
+            "kc_plan_supernodes", "kc_solve_noalloc", "kc_factor_match_bytes", "kc_factor_match_build")
 
 _LIB = None
 
@@ -100,6 +101,8 @@ def load():
         "kc_analyze_supernodal": (C.c_int, [vp, i64, i32, f64, i32, P(vp)]),
         "kc_plan_supernodes": (C.c_int, [vp, vp, P(i64)]),
         "kc_solve_noalloc": (C.c_int, [vp, vp, vp, i32, vp]),
+        "kc_factor_match_bytes": (C.c_int, [vp, vp, P(sz)]),
+        "kc_factor_match_build": (C.c_int, [vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -55,6 +55,12 @@ struct kc_factor {
     // host schedule
     std::vector<int64_t> unit_off, fwd_off, short_off, long_off, chunk_off;
     int64_t max_slots = 0;    // partial sums needed by the widest reverse level
+    // match masks (kc_factor_match_build), in a caller-owned buffer; null: index merge
+    uint64_t* mmeta = nullptr;
+    uint64_t* mwords = nullptr;
+    uint64_t mwords_n = 0;
+    uint64_t match_words = 0;  // mask words the pattern needs, once counted
+    bool match_counted = false;
     bool factorized = false;
     bool counted = false;
     hipStream_t last = nullptr;

@@ -46,7 +46,10 @@ constexpr int64_t kChunk = 512;                // entries per partial dot produc
 constexpr int kAhead = 4;                      // solve sweeps: 64-entry chunks fetched at once
 constexpr int kMaxRhsPerPass = 8;
 
-enum Counter { kNonpos = 0, kShifted = 1, kUpdates = 2, kExpHard = 3, kNonfinite = 4, kNumCounters = 8 };
+enum Counter {
+    kNonpos = 0, kShifted = 1, kUpdates = 2, kExpHard = 3, kNonfinite = 4, kMatchErr = 5, kMatchTotal = 6,
+    kNumCounters = 8
+};
 
 // ---------------------------------------------------------------------------
 // small kernels
@@ -232,7 +235,197 @@ struct IcholArgs {
     int cap;
     int nbuck;  // 0: cursor merge; else buckets of the staged row's directory (a power of 2)
     unsigned long long* counters;
+    // match masks (see match_masks_kernel), or null: per CSC entry a word offset and
+    // walk end (mmeta), and the mask words (mwords, mwords_n of them)
+    const uint64_t* mmeta;
+    const uint64_t* mwords;
+    uint64_t mwords_n;
 };
+
+// Match masks.  For an entry (k,j) below the diagonal the factorization needs
+// the parents i < j common to row k and row j, in ascending order.  Two bit
+// masks record them once per pattern: mk over row k's entries before (k,j)
+// (bit t: the row's t-th entry is a parent of j) and mj over row j's parents
+// (bit s: the s-th parent of j is in row k).  The t-th set bit of mk and the
+// t-th set bit of mj name the same i.  The entry's meta word holds the offset
+// of mk (mj follows, ceil(pos/64) words later) and, above bit kMatchOffBits,
+// one past the last set bit of mk (the walk ends there).
+constexpr int kMatchOffBits = 40;
+constexpr uint64_t kMatchOffMask = (uint64_t(1) << kMatchOffBits) - 1;
+
+// ---------------------------------------------------------------------------
+// Match masks (see factor_entries_mask), built once per pattern.
+//
+// Words of an entry e = (k,j) below the diagonal: ceil(pos/64) for mk (pos =
+// entries of row k before (k,j)) plus ceil(np/64) for mj (np = parents of j);
+// none for the diagonal.  Offsets are an exclusive prefix sum of the word
+// counts over the plan's units (each CSC entry lies in exactly one unit): a
+// block of four units scans its 256 entries in LDS (match_count_kernel), the
+// host scans the block totals, and match_base_kernel adds them.
+
+__device__ __forceinline__ uint64_t match_words_of(const int64_t* __restrict__ colptr,
+                                                   const int32_t* __restrict__ rowidx,
+                                                   const uint32_t* __restrict__ csc2csr,
+                                                   const int64_t* __restrict__ rowptr,
+                                                   const int64_t* __restrict__ rowend, int j, int64_t e) {
+    const int k = rowidx[e];
+    if (k == j) return 0;
+    const int64_t pos = int64_t(csc2csr[e]) - rowptr[k];
+    const int64_t np = rowend[j] - 1 - rowptr[j];
+    return uint64_t((pos + 63) >> 6) + uint64_t((np + 63) >> 6);
+}
+
+// Sum of the words over all entries into counters[kMatchTotal] (grid-stride over
+// units, one atomic per workgroup).
+__global__ __launch_bounds__(kBlock) void match_total_kernel(const Unit* __restrict__ units, int64_t nunits,
+                                                             const int64_t* __restrict__ colptr,
+                                                             const int32_t* __restrict__ rowidx,
+                                                             const uint32_t* __restrict__ csc2csr,
+                                                             const int64_t* __restrict__ rowptr,
+                                                             const int64_t* __restrict__ rowend,
+                                                             unsigned long long* __restrict__ counters) {
+    __shared__ unsigned long long part[kWavesPerBlock];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    unsigned long long acc = 0;
+    for (int64_t u = int64_t(blockIdx.x) * kWavesPerBlock + wave; u < nunits;
+         u += int64_t(gridDim.x) * kWavesPerBlock) {
+        const int j = units[u].col;
+        const int64_t e = colptr[j] + units[u].first + lane;
+        if (e < colptr[j + 1]) acc += match_words_of(colptr, rowidx, csc2csr, rowptr, rowend, j, e);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) t += part[w];
+        if (t) atomicAdd(counters + kMatchTotal, t);
+    }
+}
+
+// meta[e] = exclusive prefix of the words within the block; bsum[block] = block total.
+__global__ __launch_bounds__(kBlock) void match_count_kernel(const Unit* __restrict__ units, int64_t nunits,
+                                                             const int64_t* __restrict__ colptr,
+                                                             const int32_t* __restrict__ rowidx,
+                                                             const uint32_t* __restrict__ csc2csr,
+                                                             const int64_t* __restrict__ rowptr,
+                                                             const int64_t* __restrict__ rowend,
+                                                             uint64_t* __restrict__ meta, uint64_t* __restrict__ bsum) {
+    __shared__ uint64_t sc[kBlock];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t u = int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    int64_t e = -1;
+    uint64_t w = 0;
+    if (u < nunits) {
+        const int j = units[u].col;
+        e = colptr[j] + units[u].first + lane;
+        if (e < colptr[j + 1]) w = match_words_of(colptr, rowidx, csc2csr, rowptr, rowend, j, e);
+        else e = -1;
+    }
+    sc[threadIdx.x] = w;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {  // inclusive scan (Hillis-Steele)
+        const uint64_t add = threadIdx.x >= unsigned(off) ? sc[threadIdx.x - off] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (e >= 0) meta[e] = sc[threadIdx.x] - w;
+    if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = sc[threadIdx.x];
+}
+
+// meta[e] += base[block] (base: exclusive prefix of the block totals)
+__global__ __launch_bounds__(kBlock) void match_base_kernel(const Unit* __restrict__ units, int64_t nunits,
+                                                            const int64_t* __restrict__ colptr,
+                                                            const uint64_t* __restrict__ base,
+                                                            uint64_t* __restrict__ meta) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t u = int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    if (u >= nunits) return;
+    const int j = units[u].col;
+    const int64_t e = colptr[j] + units[u].first + lane;
+    if (e < colptr[j + 1]) meta[e] += base[blockIdx.x];
+}
+
+__global__ void fill_u64(uint64_t* __restrict__ p, uint64_t m, uint64_t v) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += stride) p[i] = v;
+}
+
+// The masks of one unit per wave: row j's parents staged in the wave's LDS, each
+// lane walks row k's indices before (k,j) with a cursor over them and sets a bit
+// of mk for each of its entries found in row j and the bit of mj of the parent
+// it found.  mj words a lane never reaches stay as zeroed beforehand; meta[e]
+// gets the walk end (one past the last match) above its offset.
+__global__ __launch_bounds__(kBlock) void match_masks_kernel(const Unit* __restrict__ units, int64_t nunits,
+                                                             const int64_t* __restrict__ colptr,
+                                                             const int32_t* __restrict__ rowidx,
+                                                             const uint32_t* __restrict__ csc2csr,
+                                                             const int64_t* __restrict__ rowptr,
+                                                             const int64_t* __restrict__ rowend,
+                                                             const int32_t* __restrict__ colidx, int cap,
+                                                             uint64_t* __restrict__ meta, uint64_t* __restrict__ words,
+                                                             uint64_t nwords, unsigned long long* __restrict__ counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t u = int64_t(blockIdx.x) * kWavesPerBlock + wave;
+    if (u >= nunits) return;  // whole wave; only wave-level LDS ordering below
+    int32_t* sidx = reinterpret_cast<int32_t*>(smem) + int64_t(wave) * cap;
+    const int j = __builtin_amdgcn_readfirstlane(units[u].col);
+    const int first = __builtin_amdgcn_readfirstlane(units[u].first);
+    const int64_t t0 = rowptr[j];
+    const int np = int(rowend[j] - 1 - t0);
+    for (int t = lane; t < np; t += kWave) sidx[t] = colidx[t0 + t];
+    if (lane == 0) sidx[np] = INT_MAX;
+    wave_lds_sync();
+    const int64_t e = colptr[j] + first + lane;
+    if (e >= colptr[j + 1]) return;
+    const int k = rowidx[e];
+    const uint64_t base = meta[e] & kMatchOffMask;
+    if (k == j) return;  // no walk: offset only
+    const int64_t rp = rowptr[k];
+    const int pos = int(int64_t(csc2csr[e]) - rp);
+    const int nk = (pos + 63) >> 6, nj = (np + 63) >> 6;
+    if (base + uint64_t(nk) + uint64_t(nj) > nwords) {
+        atomicAdd(counters + kMatchErr, 1ull);
+        return;
+    }
+    uint64_t* __restrict__ mk = words + base;
+    uint64_t* __restrict__ mj = mk + nk;
+    int q = 0, jcur = 0, last = -1;
+    uint64_t kw = 0, jwv = 0;
+    for (int t0w = 0; t0w < pos; t0w += 4) {
+        const int4 iv = *reinterpret_cast<const int4*>(colidx + rp + t0w);  // rows start 64-aligned
+        const int ci[4] = {iv.x, iv.y, iv.z, iv.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int t = t0w + h;
+            if (t < pos) {
+                const int i = ci[h];
+                while (sidx[q] < i) ++q;  // the sentinel stops the cursor at np
+                if (sidx[q] == i) {
+                    kw |= uint64_t(1) << (t & 63);
+                    last = t;
+                    const int qw = q >> 6;
+                    if (qw != jcur) {
+                        mj[jcur] = jwv;
+                        jcur = qw;
+                        jwv = 0;
+                    }
+                    jwv |= uint64_t(1) << (q & 63);
+                }
+                if ((t & 63) == 63) {
+                    mk[t >> 6] = kw;
+                    kw = 0;
+                }
+            }
+        }
+    }
+    if (pos & 63) mk[pos >> 6] = kw;
+    if (nj > 0) mj[jcur] = jwv;
+    meta[e] = base | (uint64_t(last + 1) << kMatchOffBits);
+}
 
 // Row j's parents (indices and L_ji) into the workgroup's LDS, staged by all its
 // threads once for every wave of the block; returns their number.
@@ -411,9 +604,151 @@ __device__ __forceinline__ void factor_entries(const IcholArgs<VT>& a, int j, in
     if (hard && active) atomicAdd(counters + kExpHard, 1ull);
 }
 
+// Row j's parent values alone (the masked factorization needs no indices).
+template <typename VT>
+__device__ __forceinline__ int stage_values(const IcholArgs<VT>& a, int j, VT* sval) {
+    const int64_t t0 = a.rowptr[j];
+    const int np = int(a.rowend[j] - 1 - t0);
+    for (int t = threadIdx.x; t < np; t += blockDim.x) sval[t] = a.Lv[t0 + t];
+    return np;
+}
+
+// factor_entries with match masks: the lane walks row k's values up to its last
+// match, and for each set bit of mk takes the next set bit of mj to find L_ji in
+// the staged row -- the same updates in the same order as the index merge, from
+// one bit per walked entry instead of a 16-bit index gap.  A value piece with
+// no set bit is not loaded.  Every loop is bounded by the masks' lengths and
+// every read checked against them, so inconsistent masks are counted
+// (kMatchErr), never followed outside row j or the mask buffer.
+template <int TWONU, bool COUNT, typename VT>
+__device__ __forceinline__ void factor_entries_mask(const IcholArgs<VT>& a, int j, int first, int np, int lane,
+                                                    const VT* sval) {
+    const int64_t* __restrict__ colptr = a.colptr;
+    const uint32_t* __restrict__ csc2csr = a.csc2csr;
+    VT* __restrict__ Lv = a.Lv;
+    const double* __restrict__ xh = a.xh;
+    const int d = a.d, policy = a.policy;
+    double ell = a.ell;
+    unsigned long long* __restrict__ counters = a.counters;
+
+    double dacc = 1.0;  // Theta_jj
+    for (int t = 0; t < np; ++t) {
+        double v = double(sval[t]);
+        dacc = __builtin_fma(-v, v, dacc);
+    }
+
+    const int64_t e = colptr[j] + first + lane;
+    const bool active = e < colptr[j + 1];
+    const int k = active ? a.rowidx[e] : j;
+    if (a.ells) ell = a.ells[a.inst[j]];
+    int hard = 0;
+    VT acc;
+    if constexpr (sizeof(VT) == 8)
+        acc = kcdev::matern<TWONU>(kcdev::dist(xh + int64_t(k) * d, xh + int64_t(j) * d, d), ell, hard);
+    else
+        acc = kcdev::matern_f32<TWONU>(float(kcdev::dist(xh + int64_t(k) * d, xh + int64_t(j) * d, d)), float(ell));
+
+    unsigned long long hits = 0;
+    bool inconsistent = false;
+    if (COUNT && active && k == j) {  // the pivot's own updates A_jj -= L_ji^2, taken from LDS above
+        for (int t = 0; t < np; ++t) hits += sval[t] != VT(0);
+    }
+    if (active && k != j) {
+        const int64_t rp = a.rowptr[k];
+        const int pos = int(int64_t(csc2csr[e]) - rp);  // row k's entries before (k,j)
+        const uint64_t m = a.mmeta[e];
+        const uint64_t base = m & kMatchOffMask;
+        const int nk = (pos + 63) >> 6, nj = (np + 63) >> 6;
+        int wend = int(m >> kMatchOffBits);
+        if (base + uint64_t(nk) + uint64_t(nj) > a.mwords_n || wend > pos) {
+            inconsistent = true;
+            wend = 0;
+        }
+        const uint64_t* __restrict__ mk = a.mwords + base;
+        const uint64_t* __restrict__ mj = mk + nk;
+        uint64_t cj = nj > 0 && wend > 0 ? mj[0] : 0, cn = nj > 1 && wend > 0 ? mj[1] : 0;
+        int jw = 0;
+        constexpr int kPiece = sizeof(VT) == 8 ? 16 : 32;  // values per 128-byte line
+        constexpr uint64_t kPieceMask = (uint64_t(1) << kPiece) - 1;
+        for (int w = 0; w * 64 < wend; ++w) {
+            const uint64_t mkw = mk[w];
+            const int64_t p = rp + int64_t(w) * 64;
+#pragma unroll
+            for (int off = 0; off < 64; off += kPiece) {
+                const uint64_t bits = (mkw >> off) & kPieceMask;
+                if (bits) {
+                    VT val[kPiece];
+                    load_vals(Lv, p + off, val);
+#pragma unroll
+                    for (int t = 0; t < kPiece; ++t) {
+                        if ((bits >> t) & 1) {
+                            while (cj == 0 && jw + 1 < nj) {
+                                ++jw;
+                                cj = cn;
+                                cn = jw + 1 < nj ? mj[jw + 1] : 0;
+                            }
+                            const int sidx = jw * 64 + (cj ? __builtin_ctzll(cj) : 0);
+                            if (cj == 0 || sidx >= np) {
+                                inconsistent = true;
+                            } else {
+                                cj &= cj - 1;
+                                const VT lji = sval[sidx];
+                                if constexpr (sizeof(VT) == 8) acc = __builtin_fma(-val[t], lji, acc);
+                                else acc = __builtin_fmaf(-val[t], lji, acc);
+                                if (COUNT && lji != VT(0)) ++hits;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    bool zero = false, shifted = false;
+    double piv = dacc;
+    if (policy == KC_PIVOT_ZERO) {
+        zero = !(piv > 0.0);
+    } else {
+        const double fl = a.tau * 1.0;
+        if (!(piv > fl)) {
+            piv = fl;
+            shifted = true;
+        }
+    }
+    const double ljj = zero ? 0.0 : __builtin_sqrt(piv);
+    bool bad = false;
+    if (active) {
+        VT out;
+        if (zero) out = VT(0);
+        else if (k == j) out = VT(ljj);
+        else if constexpr (sizeof(VT) == 8) out = acc / ljj;
+        else out = float(double(acc) / ljj);
+        Lv[csc2csr[e]] = out;
+        a.Lcsc[e] = out;
+        if constexpr (sizeof(VT) == 4)
+            if (k == j) a.diag[j] = ljj;
+        bad = !__builtin_isfinite(out);
+    }
+    const unsigned long long nf = __ballot(bad);
+    if (nf && lane == 0) atomicAdd(counters + kNonfinite, (unsigned long long)__popcll(nf));
+    const unsigned long long ni = __ballot(inconsistent);
+    if (ni && lane == 0) atomicAdd(counters + kMatchErr, (unsigned long long)__popcll(ni));
+    if (first == 0 && lane == 0) {
+        if (zero) atomicAdd(counters + kNonpos, 1ull);
+        if (shifted) atomicAdd(counters + kShifted, 1ull);
+    }
+    if (COUNT) {
+        const unsigned long long tot = wave_sum(hits);
+        if (lane == 0 && tot) atomicAdd(counters + kUpdates, tot);
+    }
+    if (hard && active) atomicAdd(counters + kExpHard, 1ull);
+}
+
 // One DAG level per launch.  A workgroup owns a block unit: 64 * WPB consecutive
 // entries of one column, 64 per wave, with the column's row staged once in LDS.
-template <int TWONU, bool COUNT, typename VT, int WPB>
+// MASK: the factorization with match masks (factor_entries_mask; only the
+// values of row j are staged); else the index merge (factor_entries).
+template <int TWONU, bool COUNT, typename VT, int WPB, bool MASK>
 __global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, const Unit* __restrict__ bunits,
                                                            int64_t ubeg, int64_t uend) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -426,23 +761,29 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, cons
     if (bu >= uend) return;  // the whole workgroup
     const int j = __builtin_amdgcn_readfirstlane(bunits[bu].col);
     const int first = __builtin_amdgcn_readfirstlane(bunits[bu].first) + wave * kWave;
-    const int np = stage_row(a, j, sval, sidx);
-    __syncthreads();
-    int shift = 0;
-    if (a.nbuck) {
-        shift = build_buckets(sidx, np, j, a.nbuck, sb);
+    if constexpr (MASK) {
+        const int np = stage_values(a, j, sval);
         __syncthreads();
-    }
-    if (a.colptr[j] + first < a.colptr[j + 1]) {
-        if (a.nbuck) factor_entries<TWONU, COUNT, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
-        else factor_entries<TWONU, COUNT, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+        if (a.colptr[j] + first < a.colptr[j + 1]) factor_entries_mask<TWONU, COUNT, VT>(a, j, first, np, lane, sval);
+    } else {
+        const int np = stage_row(a, j, sval, sidx);
+        __syncthreads();
+        int shift = 0;
+        if (a.nbuck) {
+            shift = build_buckets(sidx, np, j, a.nbuck, sb);
+            __syncthreads();
+        }
+        if (a.colptr[j] + first < a.colptr[j + 1]) {
+            if (a.nbuck) factor_entries<TWONU, COUNT, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
+            else factor_entries<TWONU, COUNT, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+        }
     }
 }
 
 // Levels [l0, l1) in one persistent launch: the workgroups of a grid that is
 // resident as a whole (cooperative launch) stride over each level's block units,
 // and a grid-wide barrier separates consecutive levels.
-template <int TWONU, bool COUNT, typename VT, int WPB>
+template <int TWONU, bool COUNT, typename VT, int WPB, bool MASK>
 __global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a, const Unit* __restrict__ bunits,
                                                                 const int64_t* __restrict__ boff, int l0, int l1) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -458,18 +799,25 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a,
         for (int64_t bu = ub + slot; bu < ue; bu += stride) {  // the same trip count for the whole workgroup
             const int j = __builtin_amdgcn_readfirstlane(bunits[bu].col);
             const int first = __builtin_amdgcn_readfirstlane(bunits[bu].first) + wave * kWave;
-            const int np = stage_row(a, j, sval, sidx);
-            __syncthreads();
-            int shift = 0;
-            if (a.nbuck) {
-                shift = build_buckets(sidx, np, j, a.nbuck, sb);
+            if constexpr (MASK) {
+                const int np = stage_values(a, j, sval);
                 __syncthreads();
-            }
-            if (a.colptr[j] + first < a.colptr[j + 1]) {
-                if (a.nbuck)
-                    factor_entries<TWONU, COUNT, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
-                else
-                    factor_entries<TWONU, COUNT, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+                if (a.colptr[j] + first < a.colptr[j + 1])
+                    factor_entries_mask<TWONU, COUNT, VT>(a, j, first, np, lane, sval);
+            } else {
+                const int np = stage_row(a, j, sval, sidx);
+                __syncthreads();
+                int shift = 0;
+                if (a.nbuck) {
+                    shift = build_buckets(sidx, np, j, a.nbuck, sb);
+                    __syncthreads();
+                }
+                if (a.colptr[j] + first < a.colptr[j + 1]) {
+                    if (a.nbuck)
+                        factor_entries<TWONU, COUNT, VT, true>(a, j, first, np, lane, sval, sidx, sb, shift);
+                    else
+                        factor_entries<TWONU, COUNT, VT, false>(a, j, first, np, lane, sval, sidx, sb, shift);
+                }
             }
             __syncthreads();  // the staged row is free again
         }
@@ -1034,10 +1382,14 @@ int32_t bucket_count(const kc::Plan& p) {
     return nb;
 }
 
-size_t factor_lds(const kc_factor* f, size_t vt) {
+// LDS of a factorization workgroup: the staged row's values, plus its indices and
+// bucket directory for the index merge (none with match masks).
+size_t factor_lds(const kc_factor* f, size_t vt, bool mask) {
+    if (mask) return (size_t(f->cap) * vt + 15) / 16 * 16;
     return (size_t(f->cap) * (vt + sizeof(int32_t)) + (f->nbuck ? size_t(f->nbuck + 1) * sizeof(uint16_t) : 0) + 15) /
            16 * 16;
 }
+size_t factor_lds(const kc_factor* f, size_t vt) { return factor_lds(f, vt, f->mmeta != nullptr); }
 
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
@@ -1066,23 +1418,26 @@ IcholArgs<VT> ichol_args(const kc_factor* f, double ell, const double* ells, int
     a.cap = f->cap;
     a.nbuck = f->nbuck;
     a.counters = f->counters;
+    a.mmeta = f->mmeta;
+    a.mwords = f->mwords;
+    a.mwords_n = f->mwords_n;
     return a;
 }
 
 // One level (block units [ub, ue)) as its own launch, or levels [l0, l1) (at
 // most maxb block units each) as one cooperative persistent launch.
-template <int TN, bool C, typename VT, int WPB>
+template <int TN, bool C, typename VT, int WPB, bool MASK>
 kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1,
                      int64_t maxb, bool persistent, hipStream_t s) {
-    const size_t lds = factor_lds(f, sizeof(VT));
+    const size_t lds = factor_lds(f, sizeof(VT), MASK);
     const int w = wpb_slot(WPB);
     if (!persistent) {
         if (ue <= ub) return KC_OK;
-        ichol_level<TN, C, VT, WPB><<<unsigned(ue - ub), WPB * kWave, lds, s>>>(a, f->bunits[f->order][w], ub, ue);
+        ichol_level<TN, C, VT, WPB, MASK><<<unsigned(ue - ub), WPB * kWave, lds, s>>>(a, f->bunits[f->order][w], ub, ue);
         KC_LAUNCH_CHECK();
         return KC_OK;
     }
-    const void* fn = reinterpret_cast<const void*>(&ichol_persistent<TN, C, VT, WPB>);
+    const void* fn = reinterpret_cast<const void*>(&ichol_persistent<TN, C, VT, WPB, MASK>);
     int per_cu = 0;
     KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WPB * kWave, lds));
     if (per_cu < 1) {
@@ -1100,12 +1455,19 @@ kc_status launch_one(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int
     return KC_OK;
 }
 
-template <int TN, bool C, typename VT>
+template <int TN, bool C, typename VT, bool MASK>
 kc_status launch_wpb(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1, int64_t maxu,
                      bool persistent, hipStream_t s) {
-    if (f->wpb == 4) return launch_one<TN, C, VT, 4>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-    if (f->wpb == 2) return launch_one<TN, C, VT, 2>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-    return launch_one<TN, C, VT, 1>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    if (f->wpb == 4) return launch_one<TN, C, VT, 4, MASK>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    if (f->wpb == 2) return launch_one<TN, C, VT, 2, MASK>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    return launch_one<TN, C, VT, 1, MASK>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+}
+
+template <int TN, bool C, typename VT>
+kc_status launch_mask(const kc_factor* f, const IcholArgs<VT>& a, int64_t ub, int64_t ue, int l0, int l1,
+                      int64_t maxu, bool persistent, hipStream_t s) {
+    if (a.mmeta) return launch_wpb<TN, C, VT, true>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+    return launch_wpb<TN, C, VT, false>(f, a, ub, ue, l0, l1, maxu, persistent, s);
 }
 
 struct NoAfter {
@@ -1121,13 +1483,13 @@ kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const 
     const IcholArgs<VT> a = ichol_args<VT>(f, ell, ells, pol, tau);
     auto go = [&](int64_t ub, int64_t ue, int l0, int l1, int64_t maxu, bool persistent) {
         if (cnt) {
-            if (tn == 1) return launch_wpb<1, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-            if (tn == 3) return launch_wpb<3, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-            return launch_wpb<5, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+            if (tn == 1) return launch_mask<1, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+            if (tn == 3) return launch_mask<3, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+            return launch_mask<5, true, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
         }
-        if (tn == 1) return launch_wpb<1, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-        if (tn == 3) return launch_wpb<3, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
-        return launch_wpb<5, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        if (tn == 1) return launch_mask<1, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        if (tn == 3) return launch_mask<3, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
+        return launch_mask<5, false, VT>(f, a, ub, ue, l0, l1, maxu, persistent, s);
     };
     const int nl = int(f->unit_off.size()) - 1;
     const std::vector<int64_t>& bo = f->boff[wpb_slot(f->wpb)];
@@ -1896,6 +2258,134 @@ kc_status kc_factor_stats(kc_factor* f, kc_factor_stats_t* st) {
     st->updates = f->counted ? int64_t(c[kUpdates]) : -1;
     st->exp_hard = int64_t(c[kExpHard]);
     st->nonfinite = int64_t(c[kNonfinite]);
+    st->match_errors = int64_t(c[kMatchErr]);
+    return KC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+uint64_t match_blocks(const kc_factor* f) { return uint64_t((f->nunits + kWavesPerBlock - 1) / kWavesPerBlock); }
+
+size_t match_bytes_of(const kc_factor* f) {
+    return align256(size_t(f->nnz) * sizeof(uint64_t)) +
+           align256(size_t(std::max<uint64_t>(match_blocks(f), 1)) * sizeof(uint64_t)) +
+           size_t(f->match_words) * sizeof(uint64_t);
+}
+
+// Reads one counter back (synchronous on s).
+kc_status read_counter(const kc_factor* f, int which, hipStream_t s, unsigned long long* out) {
+    KC_HIP(hipMemcpyAsync(out, f->counters + which, sizeof(*out), hipMemcpyDeviceToHost, s));
+    KC_HIP(hipStreamSynchronize(s));
+    return KC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+kc_status kc_factor_match_bytes(kc_factor* f, void* stream, size_t* bytes) {
+    if (!f || !bytes) return KC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!f->match_counted) {
+        unsigned long long total = 0;
+        if (f->nunits > 0) {
+            zero_u64<<<1, 64, 0, s>>>(f->counters + kMatchTotal, 1);
+            KC_LAUNCH_CHECK();
+            const unsigned g = unsigned(std::min<int64_t>(grid_for(f->nunits, kWavesPerBlock), 4096));
+            match_total_kernel<<<g, kBlock, 0, s>>>(f->units, f->nunits, f->colptr, f->rowidx, f->csc2csr, f->rowptr,
+                                                    f->rowend, f->counters);
+            KC_LAUNCH_CHECK();
+            const kc_status st = read_counter(f, kMatchTotal, s, &total);
+            if (st != KC_OK) return st;
+        }
+        f->match_words = total;
+        f->match_counted = true;
+    }
+    *bytes = match_bytes_of(f);
+    return KC_OK;
+}
+
+kc_status kc_factor_match_build(kc_factor* f, void* buf_dev, size_t bytes, void* stream) {
+    if (!f) return KC_EINVAL;
+    if (!buf_dev) {  // detach: back to the index merge
+        f->mmeta = nullptr;
+        f->mwords = nullptr;
+        f->mwords_n = 0;
+        return KC_OK;
+    }
+    size_t need = 0;
+    kc_status st = kc_factor_match_bytes(f, stream, &need);
+    if (st != KC_OK) return st;
+    if (bytes < need || reinterpret_cast<uintptr_t>(buf_dev) % 256) {
+        kc::set_error("kc_factor_match_build: the buffer must be 256-byte aligned and hold kc_factor_match_bytes (" +
+                      std::to_string(need) + ") bytes");
+        return KC_EWORKSPACE;
+    }
+    const size_t lds = size_t(kWavesPerBlock) * size_t(f->cap) * sizeof(int32_t);
+    if (lds > kMaxLdsBytes) {
+        kc::set_error("kc_factor_match_build: a row of S is too long to stage for the mask build");
+        return KC_ERANGE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(buf_dev);
+    const uint64_t nb = match_blocks(f);
+    uint64_t* meta = reinterpret_cast<uint64_t*>(base);
+    uint64_t* bsum = reinterpret_cast<uint64_t*>(base + align256(size_t(f->nnz) * sizeof(uint64_t)));
+    uint64_t* words = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(bsum) +
+                                                  align256(size_t(std::max<uint64_t>(nb, 1)) * sizeof(uint64_t)));
+    const uint64_t W = f->match_words;
+    f->mmeta = nullptr;  // the index merge until the masks are complete
+    f->mwords = nullptr;
+    f->mwords_n = 0;
+    if (f->nunits > 0) {
+        match_count_kernel<<<unsigned(nb), kBlock, 0, s>>>(f->units, f->nunits, f->colptr, f->rowidx, f->csc2csr,
+                                                          f->rowptr, f->rowend, meta, bsum);
+        KC_LAUNCH_CHECK();
+        std::vector<uint64_t> h;
+        try {
+            h.resize(size_t(nb));
+        } catch (const std::bad_alloc&) {
+            return KC_ENOMEM;
+        }
+        KC_HIP(hipMemcpyAsync(h.data(), bsum, size_t(nb) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        KC_HIP(hipStreamSynchronize(s));
+        uint64_t run = 0;
+        for (uint64_t b = 0; b < nb; ++b) {
+            const uint64_t t = h[size_t(b)];
+            h[size_t(b)] = run;
+            run += t;
+        }
+        if (run != W) {
+            kc::set_error("kc_factor_match_build: mask word counts disagree (" + std::to_string(run) + " vs " +
+                          std::to_string(W) + ")");
+            return KC_ESTATE;
+        }
+        KC_HIP(hipMemcpyAsync(bsum, h.data(), size_t(nb) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        KC_HIP(hipStreamSynchronize(s));  // h is a local buffer
+        match_base_kernel<<<unsigned(nb), kBlock, 0, s>>>(f->units, f->nunits, f->colptr, bsum, meta);
+        KC_LAUNCH_CHECK();
+        if (W > 0) {
+            fill_u64<<<unsigned(std::min<uint64_t>((W + kBlock - 1) / kBlock, 16384)), kBlock, 0, s>>>(words, W, 0);
+            KC_LAUNCH_CHECK();
+        }
+        zero_u64<<<1, 64, 0, s>>>(f->counters + kMatchErr, 1);
+        KC_LAUNCH_CHECK();
+        match_masks_kernel<<<unsigned(nb), kBlock, lds, s>>>(f->units, f->nunits, f->colptr, f->rowidx, f->csc2csr,
+                                                            f->rowptr, f->rowend, f->colidx, f->cap, meta, words, W,
+                                                            f->counters);
+        KC_LAUNCH_CHECK();
+        unsigned long long errs = 0;
+        st = read_counter(f, kMatchErr, s, &errs);
+        if (st != KC_OK) return st;
+        if (errs) {
+            kc::set_error("kc_factor_match_build: " + std::to_string(errs) + " entries fell outside the mask buffer");
+            return KC_ESTATE;
+        }
+    }
+    f->mmeta = meta;
+    f->mwords = words;
+    f->mwords_n = W;
+    f->last = s;
     return KC_OK;
 }
 

@@ -97,6 +97,18 @@ def test_factor_bitwise_in_both_unit_orders(ref, gpu):
     f.set_schedule(wpb, pm, order0)
 
 
+def test_factor_with_match_masks_bitwise(ref, gpu):
+    """The factorization with match masks (the benchmark's configuration) gives the oracle's L."""
+    f, w = gpu["f"], ref["w"]
+    nbytes = f.build_matches()
+    f.factorize(gpu["xd"], w.nu, w.lengthscale, count_updates=True)
+    st = f.stats()
+    log(f"match masks {nbytes / 1e9:.2f} GB; updates {st.updates}")
+    assert st.match_errors == 0 and st.updates == ref["R"].updates
+    assert np.array_equal(f.export_L(), ref["R"].L)
+    f.drop_matches()
+
+
 def test_solve_and_fused_call_against_oracle(ref, gpu):
     f, w = gpu["f"], ref["w"]
     f.factorize(gpu["xd"], w.nu, w.lengthscale)

@@ -78,6 +78,55 @@ def test_factor_bitwise_equal_to_oracle(K, case):
     assert bad.size == 0, f"{bad.size} of {L.size} entries of L differ; first at CSC position {bad[:5]}"
 
 
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_match_masks_factor_bitwise(K, case):
+    """With match masks (kc_factor_match_build) the factorization finds the shared parents from bits
+    instead of merging indices: L, pivot counts and the update count stay bitwise the oracle's (FP64),
+    and the mixed factor stays bitwise the index merge's."""
+    name, gen, rho, rule, nu, ell, pivot, tau = case
+    print(f"[gpu] match masks {name}", flush=True)
+    x = gen()
+    P, th, R = oracle_factor(x, rho, rule, nu, ell, O.PIVOT_ZERO if pivot == "zero" else O.PIVOT_SHIFT, tau)
+    plan = K.analyze(x, rho, rule)
+    xd = dev(x)
+    f = K.Factor(plan, "fp64")
+    nbytes = f.build_matches()
+    assert nbytes >= 8 * P.nnz
+    f.factorize(xd, nu, ell, pivot, tau, count_updates=True)
+    st = f.stats()
+    assert st.match_errors == 0 and st.exp_hard == 0
+    assert st.nonpositive == R.nonpositive and st.shifted == R.shifted and st.updates == R.updates
+    assert np.array_equal(f.export_L(), R.L)
+    mpiv, mtau = ("shift", 1e-6) if pivot == "zero" else (pivot, tau)
+    fm, fi = K.Factor(plan, "mixed"), K.Factor(plan, "mixed")
+    fm.build_matches()
+    fm.factorize(xd, nu, ell, mpiv, mtau)
+    fi.factorize(xd, nu, ell, mpiv, mtau)
+    Lm, Li = fm.export_L(), fi.export_L()
+    assert np.array_equal(np.isnan(Lm), np.isnan(Li)) and np.array_equal(Lm[~np.isnan(Li)], Li[~np.isnan(Li)])
+    assert fm.stats().match_errors == 0
+    # detaching returns to the index merge, same factor
+    f.drop_matches()
+    f.factorize(xd, nu, ell, pivot, tau)
+    assert np.array_equal(f.export_L(), R.L)
+
+
+@pytest.mark.parametrize("persist_max,order,wpb", [(2**63 - 1, "spatial", 1), (16, "longest", 2), (0, "longest", 4),
+                                                   (0, "spatial", 1)])
+def test_match_masks_under_every_schedule(K, persist_max, order, wpb):
+    print(f"[gpu] match masks schedule persist_max={persist_max} order={order} wpb={wpb}", flush=True)
+    w = W.small_uniform_2d()
+    P, th, R = oracle_factor(w.points, w.rho, "max", w.nu, w.lengthscale)
+    plan = K.analyze(w.points, w.rho)
+    f = K.Factor(plan, "fp64")
+    f.build_matches()
+    f.set_schedule(wpb, persist_max, order)
+    f.factorize(dev(w.points), w.nu, w.lengthscale, count_updates=True)
+    st = f.stats()
+    assert st.updates == R.updates and st.match_errors == 0
+    assert np.array_equal(f.export_L(), R.L)
+
+
 @pytest.mark.parametrize("limit", [1, 3, 40, 65536])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_index_gap_escapes_do_not_change_the_factor(K, limit, prec):
