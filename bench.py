@@ -5,8 +5,12 @@ Matern nu=1/2 with lengthscale 0.1, rho = 4, maximin ordering, max-rule pattern,
 8 N(0,1) right-hand sides.  One step = Theta on S fused into ICHOL(0) (one
 launch per DAG level) + the forward and backward triangular solves for all
 right-hand sides.  Points, pattern and right-hand sides are resident in HBM
-before timing starts; the host analysis (ordering, pattern, schedule) and the
-upload of the pattern are timed separately and reported beside the result.
+before timing starts; the host analysis (ordering, pattern, schedule), the
+upload of the pattern and the device-side symbolic step (the match masks, built
+once per pattern) are timed separately and reported beside the result, with the
+factorization time without the masks.  Beside the FP64 headline: the mixed
+form, its error against the FP64 factor, time to a 1e-10 CG residual for both,
+and a bounded serving run (p50/p99 latency).
 
 Prints one JSON line.  value = nnz(S) * steps / timed seconds.
 """
@@ -98,7 +102,7 @@ def algorithmic_bytes(prec, nnz, updates):
     return 8 * nnz + 8 * updates
 
 
-def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol, keep_L=False):
+def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol, keep_L=False, matches=True):
     import torch
     import paper_1706_02205_amd as K
     torch.cuda.synchronize()
@@ -112,6 +116,22 @@ def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol, keep_L=False):
     # one untimed pass that counts the Schur updates (the algorithmic work)
     f.factorize(xd, w.nu, w.lengthscale, pivot, tau, count_updates=True)
     st = f.stats()
+    # the factorization merging row indices, for reference, then the match masks (symbolic, once per
+    # pattern, like the host analysis): every timed factorization below uses them
+    t_index = None
+    match = None
+    if matches:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            f.factorize(xd, w.nu, w.lengthscale, pivot, tau)
+        b.record()
+        torch.cuda.synchronize()
+        t_index = a.elapsed_time(b) / 3 / 1e3
+        t = time.perf_counter()
+        nbytes = f.build_matches()
+        torch.cuda.synchronize()
+        match = {"build_s": time.perf_counter() - t, "bytes": nbytes}
     for _ in range(warmup):
         f.factorize(xd, w.nu, w.lengthscale, pivot, tau)
         f.solve(bd, out=out)
@@ -153,10 +173,11 @@ def run_gpu(w, prec, steps, warmup, plan, pivot, tau, pcg_tol, keep_L=False):
                   "converged": info.converged, "max_rel_residual": info.max_rel_residual,
                   "true_rel_residual": info.true_rel_residual, "restarts": info.restarts,
                   "dense_matvec_s": info.t_matvec_ms / 1e3, "precond_s": info.t_precond_ms / 1e3,
-                  "dense_pairs_per_s": n2 * info.iterations / (info.t_matvec_ms / 1e3)}
+                  # products: one per iteration plus the true-residual checks (one per restart, one at the end)
+                  "dense_pairs_per_s": n2 * (info.iterations + info.restarts + 1) / (info.t_matvec_ms / 1e3)}
     return dict(wall=wall, wall_fused=wall_fused, t_factor=t_fac, t_solve=t_sol, updates=st.updates, rank=st2.rank,
                 nonpositive=st2.nonpositive, shifted=st2.shifted, exp_hard=st2.exp_hard, nonfinite=st2.nonfinite,
-                t_upload=t_upload,
+                match_errors=st2.match_errors, t_upload=t_upload, t_index=t_index, match=match,
                 workspace_bytes=f.workspace_bytes, refine=refine, L=f.export_L() if keep_L else None,
                 schedule=dict(zip(("waves_per_block", "persist_max", "unit_order"), f.schedule())))
 
@@ -247,37 +268,17 @@ def run_serving(args):
     resident within a 64 GB nnz(S)-proportional budget.  The capacity is measured first (every request
     arriving at once); the same requests are then replayed at 0.5, 0.8 and 1.0 times that rate.  The
     value is p50 latency at 0.8 x capacity; p50/p99 and throughput are reported for every rate."""
-    from paper_1706_02205_amd import serve
-    from paper_1706_02205_amd import workloads as W
-    reqs = W.serving_trace(args.requests, 1.0)  # arrivals for rate 1/s; scaled below
-    pts = [r.points for r in reqs]
-    rhs = [W.gaussian_rhs(len(r.points), 4, r.rhs_seed) for r in reqs]
-
-    def serve_at(rate):
-        scale = 0.0 if rate is None else 1.0 / rate
-        trace = [(r.arrival_s * scale, p, b) for r, p, b in zip(reqs, pts, rhs)]
-        srv = serve.Server(1.5, 0.2, 3.0, prec="mixed", budget_bytes=64e9, max_inflight=16, nstreams=4,
-                           analysis_threads=args.analysis_threads)
-        st = srv.run(trace)
-        srv.close()
-        return st.summary()
-
-    cap = serve_at(None)["throughput_req_s"]
-    log(f"[bench] serving capacity (all {len(reqs)} requests at once): {cap:.2f} requests/s")
-    runs = []
-    for frac in (0.5, 0.8, 1.0):
-        s = serve_at(frac * cap)
-        s["rate_per_s"] = frac * cap
-        s["load"] = frac
-        runs.append(s)
-        log(f"[bench] serving at {frac:.1f} x capacity ({frac * cap:.2f}/s): p50 {s['p50_ms']:.1f} ms, "
-            f"p99 {s['p99_ms']:.1f} ms, {s['throughput_req_s']:.2f} requests/s")
+    cap, runs = serve_run(args.requests, args.analysis_threads, (0.5, 0.8, 1.0))
+    log(f"[bench] serving capacity (all {args.requests} requests at once): {cap:.2f} requests/s")
+    for sm in runs:
+        log(f"[bench] serving at {sm['load']:.1f} x capacity ({sm['rate_per_s']:.2f}/s): p50 {sm['p50_ms']:.1f} ms, "
+            f"p99 {sm['p99_ms']:.1f} ms, {sm['throughput_req_s']:.2f} requests/s")
     head = runs[1]
     print(json.dumps({
-        "metric": "serve p50/p99 ms", "value": head["p50_ms"], "unit": "ms", "n_gpus": 1, "steps": len(reqs),
+        "metric": "serve p50/p99 ms", "value": head["p50_ms"], "unit": "ms", "n_gpus": 1, "steps": args.requests,
         "warmup": 0, "ms_per_step": head["mean_ms"], "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32-updates/f64-pivots", "data": "synthetic",
-        "config": {"workload": f"serve-sincos20d-{len(reqs)}req-load0.8", "rate_per_s": head["rate_per_s"],
+        "config": {"workload": f"serve-sincos20d-{args.requests}req-load0.8", "rate_per_s": head["rate_per_s"],
                    "capacity_req_s": cap, "n_range": [1000, 200000], "nrhs": 4, "budget_bytes": 64e9},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "throughput_req_s": head["throughput_req_s"],
         "s_entries_per_s": head["s_entries_per_s"], "peak_inflight": head["peak_inflight"],
@@ -312,6 +313,76 @@ def sampled_error(plan, points, L, nu, ell, npairs, seed):
         num += float(((llt - th) ** 2).sum())
         den += float((th ** 2).sum())
     return float(np.sqrt(num / den))
+
+
+def factor_error_report(plan, points, L64, Lmx, nu, ell, npairs=200_000, seed=1007):
+    """The mixed factor against the FP64 factor at full size (the FP64 factor is the oracle's bit for bit
+    wherever the oracle can run, see tests/test_gpu_fullpath_250k.py): per column max_k |dL_kj| / max_k |L_kj|
+    and ||dL||_F / ||L||_F, plus the sampled error E of Section 4.4 for both factors over the same pairs."""
+    import scipy.sparse as sp
+    from paper_1706_02205_amd import workloads as W
+    perm, _, colptr, rowidx = plan.export()
+    n, nnz = len(perm), int(colptr[-1])
+    dL = np.abs(Lmx - L64)
+    col_err = np.maximum.reduceat(dL, colptr[:-1])
+    col_max = np.maximum.reduceat(np.abs(L64), colptr[:-1])
+    per_col = col_err / np.where(col_max > 0, col_max, 1.0)
+    frob = float(np.linalg.norm(Lmx - L64) / np.linalg.norm(L64))
+    del dL
+    # rows of L (CSR) for (LL^T)_ab = row a . row b; the CSC -> CSR permutation once for both factors
+    idx = sp.csc_matrix((np.arange(nnz, dtype=np.float64), rowidx, colptr), shape=(n, n)).tocsr()
+    order = idx.data.astype(np.int64)
+    xh = points[perm]
+    pairs = W.random_pairs(n, npairs, seed)
+    out = {"per_column_max_rel": float(per_col.max()), "per_column_median_rel": float(np.median(per_col)),
+           "frobenius_rel": frob, "sampled_pairs": npairs}
+    for name, L in (("fp64", L64), ("mixed", Lmx)):
+        Lr = sp.csr_matrix((L[order], idx.indices, idx.indptr), shape=(n, n))
+        num = den = 0.0
+        for c in range(0, npairs, 20000):
+            a, b = pairs[c:c + 20000, 0], pairs[c:c + 20000, 1]
+            llt = np.asarray(Lr[a].multiply(Lr[b]).sum(axis=1)).ravel()
+            r = np.sqrt(((xh[a] - xh[b]) ** 2).sum(axis=1)) / ell
+            if nu == 0.5:
+                th = np.exp(-r)
+            elif nu == 1.5:
+                th = (1 + np.sqrt(3) * r) * np.exp(-np.sqrt(3) * r)
+            else:
+                th = (1 + np.sqrt(5) * r + 5 * r * r / 3) * np.exp(-np.sqrt(5) * r)
+            num += float(((llt - th) ** 2).sum())
+            den += float((th ** 2).sum())
+        out[f"sampled_E_{name}"] = float(np.sqrt(num / den))
+    return out
+
+
+def serve_run(requests, analysis_threads, loads=(0.8,)):
+    """Poisson arrivals of factor+solve requests (N log-uniform in [1e3, 2e5], points of intrinsic
+    dimension 2 in R^20, Matern-3/2 l=0.2, rho=3, 4 right-hand sides, mixed precision, 64 GB of resident
+    factors at most).  Capacity first (every request arriving at once), then the same requests at each
+    load fraction of it; p50/p99 latency (arrival -> solution on the host) and throughput."""
+    from paper_1706_02205_amd import serve
+    from paper_1706_02205_amd import workloads as W
+    reqs = W.serving_trace(requests, 1.0)  # arrivals for rate 1/s; scaled below
+    pts = [r.points for r in reqs]
+    rhs = [W.gaussian_rhs(len(r.points), 4, r.rhs_seed) for r in reqs]
+
+    def serve_at(rate):
+        scale = 0.0 if rate is None else 1.0 / rate
+        trace = [(r.arrival_s * scale, p, b) for r, p, b in zip(reqs, pts, rhs)]
+        srv = serve.Server(1.5, 0.2, 3.0, prec="mixed", budget_bytes=64e9, max_inflight=16, nstreams=4,
+                           analysis_threads=analysis_threads)
+        st = srv.run(trace)
+        srv.close()
+        return st.summary()
+
+    cap = serve_at(None)["throughput_req_s"]
+    runs = []
+    for frac in loads:
+        sm = serve_at(frac * cap)
+        sm["rate_per_s"] = frac * cap
+        sm["load"] = frac
+        runs.append(sm)
+    return cap, runs
 
 
 def run_supernodal(args):
@@ -396,6 +467,12 @@ def main():
                     help="grid: the 10^6-point benchmark (default); batched: 512 independent instances; "
                          "serve: Poisson trace of factor+solve requests; dense: the dense Theta product alone")
     ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="grid workload: also serve this many requests at 0.8 x measured capacity (0 = skip)")
+    ap.add_argument("--error-pairs", type=int, default=200_000,
+                    help="grid workload: sampled pairs for the mixed-vs-FP64 error report (0 = skip)")
+    ap.add_argument("--no-matches", action="store_true",
+                    help="factor without match masks (index merge), e.g. to compare")
     ap.add_argument("--analysis-threads", type=int, default=12)
     ap.add_argument("--instances", type=int, default=512)
     args = ap.parse_args()
@@ -444,9 +521,12 @@ def main():
     precs = ["fp64", "mixed"] if args.prec == "both" else [args.prec]
     nnz = info["nnz"]
     entries = {}
+    factors = {}
     for prec in precs:
         pivot, tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
-        r = run_gpu(w, prec, args.steps, args.warmup, plan, pivot, tau, args.pcg_tol)
+        r = run_gpu(w, prec, args.steps, args.warmup, plan, pivot, tau, args.pcg_tol,
+                    keep_L=args.error_pairs > 0 and len(precs) == 2, matches=not args.no_matches)
+        factors[prec] = r.pop("L")
         # a step is factorize + solve: as two calls, or as the fused call that overlaps the forward sweep
         # with the factorization (bitwise the same result); the faster of the two is the step
         step_sep, step_fused = r["wall"] / args.steps, r["wall_fused"] / args.steps
@@ -455,6 +535,9 @@ def main():
         tf = float(np.mean(r["t_factor"]))
         ts = float(np.mean(r["t_solve"]))
         log(f"[bench] {prec}: factor {tf * 1e3:.2f} ms  solve {ts * 1e3:.2f} ms  updates={r['updates']}")
+        if r["match"]:
+            log(f"[bench] {prec}: match masks {r['match']['bytes'] / 1e9:.1f} GB built in {r['match']['build_s']:.2f} s; "
+                f"factor without them {r['t_index'] * 1e3:.2f} ms")
         B = algorithmic_bytes(prec, nnz, r["updates"])
         launches = info["nlevels"]
         achieved = (B / launches) / (tf / launches) / 1e9
@@ -466,14 +549,19 @@ def main():
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                          "measured_copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                         "kernel": "ichol_level (Theta fused), one launch per DAG level",
+                         "kernel": ("ichol_level (Theta fused, match masks)" if r["match"] else
+                                    "ichol_level (Theta fused, index merge)") + ", one launch per DAG level",
                          "launches_per_factorization": launches,
                          "algorithmic_bytes_per_launch": B / launches,
                          "avg_launch_ms": tf / launches * 1e3},
             "factor_only": {"value": nnz / tf, "unit": "S-entries/s", "ms": tf * 1e3},
             "solve_ms": ts * 1e3, "updates": r["updates"], "rank": r["rank"], "nonpositive": r["nonpositive"],
-            "shifted": r["shifted"], "exp_hard": r["exp_hard"], "nonfinite": r["nonfinite"], "upload_s": r["t_upload"],
+            "shifted": r["shifted"], "exp_hard": r["exp_hard"], "nonfinite": r["nonfinite"],
+            "match_errors": r["match_errors"], "upload_s": r["t_upload"],
             "workspace_bytes": r["workspace_bytes"], "schedule": r["schedule"],
+            # symbolic match masks: built once per pattern (like the host analysis), not in the timed steps
+            "match_masks": r["match"],
+            "factor_ms_without_masks": r["t_index"] * 1e3 if r["t_index"] is not None else None,
         }
         if r["refine"] is not None:
             entries[prec]["refine"] = r["refine"]
@@ -509,6 +597,27 @@ def main():
         result["refine"] = head["refine"]
     if "mixed" in entries and precs[0] != "mixed":
         result["mixed"] = entries["mixed"]
+        if factors.get("fp64") is not None and factors.get("mixed") is not None:
+            t = time.perf_counter()
+            rep = factor_error_report(plan, w.points, factors["fp64"], factors["mixed"], w.nu, w.lengthscale,
+                                      args.error_pairs)
+            log(f"[bench] mixed vs fp64 factor: per-column max rel {rep['per_column_max_rel']:.2e}, Frobenius "
+                f"{rep['frobenius_rel']:.2e}; sampled E fp64 {rep['sampled_E_fp64']:.3e} mixed "
+                f"{rep['sampled_E_mixed']:.3e} ({time.perf_counter() - t:.1f} s)")
+            result["mixed"]["error_vs_fp64"] = rep
+    factors.clear()
+    if args.serve_requests > 0:
+        # the second half of the metric: serving latency, a bounded run at 0.8 x the capacity measured here
+        t = time.perf_counter()
+        cap, runs = serve_run(args.serve_requests, args.analysis_threads, (0.8,))
+        sm = runs[0]
+        log(f"[bench] serving {args.serve_requests} requests: capacity {cap:.2f}/s; at 0.8 x: p50 {sm['p50_ms']:.1f} ms "
+            f"p99 {sm['p99_ms']:.1f} ms, {sm['throughput_req_s']:.2f} requests/s ({time.perf_counter() - t:.1f} s)")
+        result["serve"] = {"workload": f"serve-sincos20d-{args.serve_requests}req", "requests": args.serve_requests,
+                           "capacity_req_s": cap, "load": 0.8, "rate_per_s": sm["rate_per_s"],
+                           "p50_ms": sm["p50_ms"], "p99_ms": sm["p99_ms"], "throughput_req_s": sm["throughput_req_s"],
+                           "peak_inflight": sm["peak_inflight"], "prec": "mixed", "nrhs": 4,
+                           "n_range": [1000, 200000]}
     if args.cpu_grid > 0:
         log(f"[bench] CPU baseline: oracle at {args.cpu_grid}x{args.cpu_grid}")
         result["cpu_baseline"] = cpu_baseline(args.cpu_grid)
