@@ -670,8 +670,10 @@ __device__ __forceinline__ void factor_entries_mask(const IcholArgs<VT>& a, int 
         int jw = 0;
         constexpr int kPiece = sizeof(VT) == 8 ? 16 : 32;  // values per 128-byte line
         constexpr uint64_t kPieceMask = (uint64_t(1) << kPiece) - 1;
+        uint64_t mkn = wend > 0 ? mk[0] : 0;
         for (int w = 0; w * 64 < wend; ++w) {
-            const uint64_t mkw = mk[w];
+            const uint64_t mkw = mkn;
+            mkn = (w + 1) * 64 < wend ? mk[w + 1] : 0;  // the next window's bits, in flight meanwhile
             const int64_t p = rp + int64_t(w) * 64;
 #pragma unroll
             for (int off = 0; off < 64; off += kPiece) {
