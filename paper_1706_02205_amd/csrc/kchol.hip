@@ -43,7 +43,6 @@ constexpr int kBlock = 256;                    // 4 wavefronts
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int64_t kLongColumn = 2048;          // backward solve: longer columns are reduced in pieces
 constexpr int64_t kChunk = 512;                // entries per partial dot product of a long column
-constexpr int kAhead = 4;                      // solve sweeps: 64-entry chunks fetched at once
 constexpr int kMaxRhsPerPass = 8;
 
 enum Counter {
@@ -865,6 +864,55 @@ __device__ __forceinline__ double apply_chunk(const double* __restrict__ sL, con
     return acc;
 }
 
+// acc - sum over entries p in [b0, b1) of val[p] * src[idx[p]] (one value per
+// right-hand side), applied in ascending p by lanes r < NR -- the sequential
+// substitution.  The indices and values of kGroup 64-entry chunks are fetched at
+// once; then each chunk's gathered right-hand-side rows are requested before the
+// previous chunk is applied, so the gathers overlap the dependent fmas.
+constexpr int kGroup = 6;  // 384 entries: a whole row of the 2-D benchmark in one fetch
+
+template <int NR>
+__device__ __forceinline__ void gather_chunk(const double* __restrict__ src, int ld, int r0, int i, double (&v)[NR]) {
+    if (i >= 0) {
+        const double* si = src + int64_t(i) * ld + r0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = si[r];
+    }
+}
+
+template <typename VT, int NR>
+__device__ __forceinline__ double substitute(const int32_t* __restrict__ idx, const VT* __restrict__ val, int64_t b0,
+                                             int64_t b1, const double* __restrict__ src, int ld, int r0, int lane,
+                                             double* sL, double* sY, double acc) {
+    for (int64_t cb = b0; cb < b1; cb += kGroup * kWave) {
+        int ci[kGroup];
+        double lv[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int64_t p = cb + int64_t(u) * kWave + lane;
+            ci[u] = p < b1 ? idx[p] : -1;
+            lv[u] = p < b1 ? double(val[p]) : 0.0;
+        }
+        double yv[2][NR];
+        gather_chunk<NR>(src, ld, r0, ci[0], yv[0]);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int64_t c = cb + int64_t(u) * kWave;
+            if (c >= b1) break;
+            if (u + 1 < kGroup) gather_chunk<NR>(src, ld, r0, ci[u + 1 < kGroup ? u + 1 : u], yv[(u + 1) & 1]);
+            if (ci[u] >= 0) {
+                sL[lane] = lv[u];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) sY[lane * NR + r] = yv[u & 1][r];
+            }
+            wave_lds_sync();
+            if (lane < NR) acc = apply_chunk<NR>(sL, sY, int(b1 - c < kWave ? b1 - c : kWave), lane, acc);
+            wave_lds_sync();
+        }
+    }
+    return acc;
+}
+
 template <typename VT, int NR>
 __global__ __launch_bounds__(kBlock) void fwd_solve(const int32_t* __restrict__ rows, int64_t beg, int64_t end,
                                                     const int64_t* __restrict__ rowptr,
@@ -883,39 +931,8 @@ __global__ __launch_bounds__(kBlock) void fwd_solve(const int32_t* __restrict__ 
     const int64_t p0 = rowptr[k], pd = rowend[k] - 1;  // pd: the diagonal
     double acc = 0.0;
     if (lane < NR) acc = b[int64_t(perm[k]) * ld + r0 + lane];
-    // kAhead chunks of the row are fetched at once -- their indices and L values,
-    // then the gathered right-hand-side rows (parents' values are final: earlier
-    // levels) -- so a row costs two memory latencies per kAhead * 64 entries
-    for (int64_t cb = p0; cb < pd; cb += kAhead * kWave) {
-        int ci[kAhead];
-        double lv[kAhead], yv[kAhead][NR];
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u) {
-            const int64_t p = cb + int64_t(u) * kWave + lane;
-            ci[u] = p < pd ? colidx[p] : -1;
-            lv[u] = p < pd ? double(Lv[p]) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u)
-            if (ci[u] >= 0) {
-                const double* yi = y + int64_t(ci[u]) * ld + r0;
-#pragma unroll
-                for (int r = 0; r < NR; ++r) yv[u][r] = yi[r];
-            }
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u) {
-            const int64_t c = cb + int64_t(u) * kWave;
-            if (c >= pd) break;
-            if (ci[u] >= 0) {
-                sL[wave][lane] = lv[u];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = yv[u][r];
-            }
-            wave_lds_sync();
-            if (lane < NR) acc = apply_chunk<NR>(sL[wave], sY[wave], int(pd - c < kWave ? pd - c : kWave), lane, acc);
-            wave_lds_sync();
-        }
-    }
+    // parents' values are final: earlier levels
+    acc = substitute<VT, NR>(colidx, Lv, p0, pd, y, ld, r0, lane, sL[wave], sY[wave], acc);
     if (lane < NR) {
         const double lkk = diag_value(Lv, diag, pd, k);
         y[int64_t(k) * ld + r0 + lane] = (lkk == 0.0) ? 0.0 : acc / lkk;
@@ -939,38 +956,8 @@ __global__ __launch_bounds__(kBlock) void bwd_solve(const int32_t* __restrict__ 
     const int64_t c0 = colptr[j], c1 = colptr[j + 1];
     double acc = 0.0;
     if (lane < NR) acc = y[int64_t(j) * ld + r0 + lane];
-    // kAhead chunks fetched at once, as in the forward sweep (rows below j are
-    // final: earlier reverse levels)
-    for (int64_t cb = c0 + 1; cb < c1; cb += kAhead * kWave) {
-        int ri[kAhead];
-        double lv[kAhead], yv[kAhead][NR];
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u) {
-            const int64_t e = cb + int64_t(u) * kWave + lane;
-            ri[u] = e < c1 ? rowidx[e] : -1;
-            lv[u] = e < c1 ? double(Lcsc[e]) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u)
-            if (ri[u] >= 0) {
-                const double* xk = y + int64_t(ri[u]) * ld + r0;
-#pragma unroll
-                for (int r = 0; r < NR; ++r) yv[u][r] = xk[r];
-            }
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u) {
-            const int64_t c = cb + int64_t(u) * kWave;
-            if (c >= c1) break;
-            if (ri[u] >= 0) {
-                sL[wave][lane] = lv[u];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) sY[wave][lane * NR + r] = yv[u][r];
-            }
-            wave_lds_sync();
-            if (lane < NR) acc = apply_chunk<NR>(sL[wave], sY[wave], int(c1 - c < kWave ? c1 - c : kWave), lane, acc);
-            wave_lds_sync();
-        }
-    }
+    // rows below j are final: earlier reverse levels
+    acc = substitute<VT, NR>(rowidx, Lcsc, c0 + 1, c1, y, ld, r0, lane, sL[wave], sY[wave], acc);
     if (lane < NR) {
         const double ljj = diag_value(Lcsc, diag, c0, j);
         const double v = (ljj == 0.0) ? 0.0 : acc / ljj;
