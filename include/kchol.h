@@ -282,6 +282,20 @@ void kc_factor_destroy(kc_factor *f);
 kc_status kc_factor_set_schedule(kc_factor *f, int32_t wpb, int64_t persist_max, kc_unit_order order);
 kc_status kc_factor_schedule(const kc_factor *f, int32_t *wpb, int64_t *persist_max, kc_unit_order *order);
 
+/* Supernodal groups on the matrix cores (mixed-precision factors of supernodal
+ * plans, kc_analyze_supernodal; the default for them).  The block-closed
+ * pattern gives every member of a supernode the same row structure (Section 5,
+ * the supernodal construction; its factorization is the supernodal incomplete
+ * Cholesky of the appendix), so a group of up to 16 consecutive members shares
+ * its parents: each row below the group is walked once for the whole group, and
+ * the group's Schur update is a dense FP32 product on MFMA
+ * (v_mfma_f32_16x16x4f32), followed by the group's dense diagonal block with
+ * FP64 pivots.  The levels are those of the group DAG.  Update counting, FP64
+ * factors and other plans use the entry-wise factorization.  enable = 0 selects
+ * the entry-wise factorization for this factor too (results differ only by
+ * FP32 rounding order).  KC_EINVAL when enabling on a factor without groups. */
+kc_status kc_factor_use_groups(kc_factor *f, int32_t enable);
+
 /* Autotuner: times the factorization (reps repetitions after a warm-up) for
  * every schedule in {1, 2, 4} wavefronts per workgroup x level grouping
  * persist_max in {0, 256, 4096, all levels} x unit order {SPATIAL, LONGEST} --

@@ -241,6 +241,11 @@ class Factor:
         _lib.check(_lib.load().kc_factor_set_schedule(self._h, int(wpb), int(persist_max), _ORDERS[order]),
                    "kc_factor_set_schedule")
 
+    def use_groups(self, enable: bool = True) -> None:
+        """Factor a mixed-precision supernodal plan by supernodal groups on the matrix cores (the default for
+        such factors) or entry by entry (enable=False)."""
+        _lib.check(_lib.load().kc_factor_use_groups(self._h, int(bool(enable))), "kc_factor_use_groups")
+
     def schedule(self) -> tuple:
         """(wavefronts per workgroup, persist_max, unit order) in use -- the tuner's choice after tune()."""
         w, pm, o = C.c_int32(), C.c_int64(), C.c_int()

@@ -51,6 +51,11 @@ struct kc_factor {
     kc::LongCol* bwd_long = nullptr;
     kc::BwdChunk* bwd_chunks = nullptr;
     int32_t* inst = nullptr;   // instance of each position (batches only)
+    // supernodal groups on the matrix cores (mixed precision, supernodal plans)
+    kc::GroupDesc* groups = nullptr;
+    int2* gunits = nullptr;
+    std::vector<int64_t> goff;
+    bool use_groups = false;
     int32_t ninst = 1;
     // host schedule
     std::vector<int64_t> unit_off, fwd_off, short_off, long_off, chunk_off;

@@ -827,6 +827,209 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a,
 }
 
 // ---------------------------------------------------------------------------
+// Supernodal groups on the matrix cores (mixed precision, supernodal plans).
+//
+// The block-closed pattern makes every member of a supernode J = [s0, s1) share
+// one row structure: row g of a member is P(J) (the parents of s0), then s0..g-1;
+// column g is g..s1-1, then the rows O_J of the other supernodes below J.  A
+// group G = [g0, g1) of at most 16 consecutive members therefore shares its
+// parents P_G = row g0 before its diagonal, and for a row k of column g0 the
+// Schur updates of all 16 entries (k, g), g in G, run over the same parents
+// i in P_G that row k holds:
+//     a_kg = Theta_kg - sum_{i in P_G, i in row k} L_ki L_gi - sum_{g0 <= h < g} L_kh L_gh.
+// The first sum, for 64 rows at once, is a dense product (64 x |P_G|) . (|P_G| x 16)
+// on v_mfma_f32_16x16x4f32: row k's values are scattered into an LDS tile over
+// P_G (row k is walked once for the whole group, instead of once per column as
+// in the element-wise kernel) and the group's rows L_{G,P_G} form the other
+// operand.  The second sum and the divisions follow in registers, column by
+// column: the dense Cholesky of the group's diagonal block with FP64 pivots
+// (accumulated as in the element-wise kernel, FP32 x FP32 products exact in
+// FP64), then the panel rows.  A unit is one group with its 16 diagonal rows
+// (recomputed by every unit of the group, written by the first) and 48 panel
+// rows; the units of a level of the group DAG run in one launch.
+constexpr int kGroupCols = 16;  // columns of a group: the width of the MFMA tile
+constexpr int kGroupRows = 48;  // panel rows of a unit, beside the group's 16 diagonal rows
+constexpr int kGroupKC = 64;    // parents per LDS chunk
+
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int TWONU>
+__global__ __launch_bounds__(kWave) void ichol_group(IcholArgs<float> a, const kc::GroupDesc* __restrict__ groups,
+                                                     const int2* __restrict__ gunits, int64_t ubeg, int64_t uend) {
+    __shared__ float As[kWave][kGroupKC + 1];
+    __shared__ float Bs[kGroupCols][kGroupKC + 1];
+    __shared__ float Cs[kWave][kGroupCols + 1];
+    __shared__ float Ld[kGroupCols][kGroupCols + 1];
+    __shared__ double piv[kGroupCols];
+    __shared__ int pzero[kGroupCols];
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t* sP = reinterpret_cast<int32_t*>(smem);  // the group's parents, then a sentinel
+    const int lane = threadIdx.x;
+    const int64_t u = ubeg + int64_t(blockIdx.x);
+    if (u >= uend) return;
+    const int2 gu = gunits[u];
+    const kc::GroupDesc G = groups[gu.x];
+    const int tile = gu.y;
+    const int g0 = G.g0, m = G.g1 - G.g0;
+    const int64_t t0 = a.rowptr[g0];
+    const int np = int(a.rowend[g0] - 1 - t0);
+    for (int t = lane; t < np; t += kWave) sP[t] = a.colidx[t0 + t];
+    if (lane == 0) sP[np] = INT_MAX;
+    // this lane's row: lanes 0..15 the group's diagonal rows g0 + lane, lanes 16..63 panel rows
+    const int64_t cg0 = a.colptr[g0];
+    int k = -1;
+    int64_t eoff = -1;  // offset of (k, g0) in column g0
+    if (lane < kGroupCols) {
+        if (lane < m) {
+            k = g0 + lane;
+            eoff = lane;
+        }
+    } else {
+        const int64_t pr = int64_t(tile) * kGroupRows + (lane - kGroupCols);
+        if (pr < G.nb) {
+            eoff = m + pr;
+            k = a.rowidx[cg0 + eoff];
+        }
+    }
+    const bool panel = lane >= kGroupCols && k >= 0;
+    int64_t p = 0, pend = 0;  // the walk of row k before (k, g0)
+    int q = 0;                // cursor over the parents
+    if (panel) {
+        p = a.rowptr[k];
+        pend = a.csc2csr[cg0 + eoff];
+    }
+    wave_lds_sync();
+
+    mfma_f4 acc[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    double dd = 1.0;  // pivot of diagonal row `lane`: Theta_jj = 1 minus the squares, ascending
+    for (int c0 = 0; c0 < np; c0 += kGroupKC) {
+        const int cn = np - c0 < kGroupKC ? np - c0 : kGroupKC;
+        for (int idx = lane; idx < kGroupCols * kGroupKC; idx += kWave) {
+            const int g = idx / kGroupKC, qq = idx % kGroupKC;
+            Bs[g][qq] = (g < m && qq < cn) ? a.Lv[a.rowptr[g0 + g] + c0 + qq] : 0.f;
+        }
+#pragma unroll
+        for (int qq = 0; qq < kGroupKC; ++qq) As[lane][qq] = 0.f;
+        wave_lds_sync();
+        if (lane < m) {  // a diagonal row's prefix is P_G itself
+            for (int qq = 0; qq < cn; ++qq) {
+                const float v = Bs[lane][qq];
+                As[lane][qq] = v;
+                dd = __builtin_fma(-double(v), double(v), dd);
+            }
+        }
+        bool more = panel && p < pend;
+        while (more) {  // eight entries of row k per load, from an 8-aligned start (rows are 64-aligned)
+            const int64_t bp = p & ~int64_t(7);
+            const int4 ia = *reinterpret_cast<const int4*>(a.colidx + bp);
+            const int4 ib = *reinterpret_cast<const int4*>(a.colidx + bp + 4);
+            const float4 va = *reinterpret_cast<const float4*>(a.Lv + bp);
+            const float4 vb = *reinterpret_cast<const float4*>(a.Lv + bp + 4);
+            const int ii[8] = {ia.x, ia.y, ia.z, ia.w, ib.x, ib.y, ib.z, ib.w};
+            const float vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                if (more && bp + h >= p) {
+                    if (bp + h >= pend) {
+                        more = false;
+                    } else {
+                        const int i = ii[h];
+                        while (sP[q] < i) ++q;  // the sentinel stops at np
+                        if (q >= c0 + cn) {
+                            more = false;  // a later chunk: resume here
+                        } else {
+                            if (sP[q] == i) As[lane][q - c0] = vv[h];
+                            p = bp + h + 1;
+                        }
+                    }
+                }
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int ks = 0; ks < kGroupKC / 4; ++ks) {
+            const int kk = ks * 4 + lane / 16, col = lane % 16;
+            const float bv = Bs[col][kk];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[rb * 16 + col][kk], bv, acc[rb], 0, 0, 0);
+        }
+        wave_lds_sync();
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Cs[rb * 16 + 4 * (lane / 16) + i][lane % 16] = acc[rb][i];
+    wave_lds_sync();
+
+    // external part: a_g = Theta_kg - C_kg
+    float av[kGroupCols], Lr[kGroupCols];
+    double ell = a.ell;
+#pragma unroll
+    for (int g = 0; g < kGroupCols; ++g) {
+        av[g] = 0.f;
+        Lr[g] = 0.f;
+        if (k >= 0 && g < m && k != g0 + g) {
+            const float th = kcdev::matern_f32<TWONU>(
+                float(kcdev::dist(a.xh + int64_t(k) * a.d, a.xh + int64_t(g0 + g) * a.d, a.d)), float(ell));
+            av[g] = th - Cs[lane][g];
+        }
+    }
+    // the group's columns in order: pivot from diagonal lane g, then the rows below
+#pragma unroll
+    for (int g = 0; g < kGroupCols; ++g) {
+        if (g < m) {
+            if (lane == g) {
+                double pd = dd;
+#pragma unroll
+                for (int h = 0; h < g; ++h) pd = __builtin_fma(-double(Lr[h]), double(Lr[h]), pd);
+                bool zero = false;
+                if (a.policy == KC_PIVOT_ZERO) {
+                    zero = !(pd > 0.0);
+                } else if (!(pd > a.tau)) {
+                    pd = a.tau;
+                    if (tile == 0) atomicAdd(a.counters + kShifted, 1ull);
+                }
+                if (zero && tile == 0) atomicAdd(a.counters + kNonpos, 1ull);
+                piv[g] = zero ? 0.0 : __builtin_sqrt(pd);
+                pzero[g] = zero;
+            }
+            wave_lds_sync();
+            const double ljj = piv[g];
+            const bool zero = pzero[g] != 0;
+            if ((lane < m && lane > g) || panel) {
+                float x = av[g];
+#pragma unroll
+                for (int h = 0; h < g; ++h) x = __builtin_fmaf(-Lr[h], Ld[g][h], x);
+                Lr[g] = zero ? 0.f : float(double(x) / ljj);
+                if (lane < m) Ld[lane][g] = Lr[g];
+            }
+            wave_lds_sync();
+        }
+    }
+    // write: panel rows by every unit, the diagonal block by the group's first unit
+    bool bad = false;
+    if (k >= 0 && (panel || tile == 0)) {
+#pragma unroll
+        for (int g = 0; g < kGroupCols; ++g) {
+            if (g < m && (panel || lane >= g)) {
+                const int j = g0 + g;
+                const int64_t e = k < G.s1 ? a.colptr[j] + (k - j) : a.colptr[j] + (G.s1 - j) + (eoff - (G.s1 - g0));
+                const float out = lane == g ? float(piv[g]) : Lr[g];
+                a.Lcsc[e] = out;
+                a.Lv[a.csc2csr[e]] = out;
+                if (lane == g) a.diag[j] = piv[g];
+                bad = bad || !__builtin_isfinite(out);
+            }
+        }
+    }
+    const unsigned long long nf = __ballot(bad);
+    if (nf && lane == 0) atomicAdd(a.counters + kNonfinite, (unsigned long long)__popcll(nf));
+}
+
+// ---------------------------------------------------------------------------
 // A3: y = L^{-1} P b by rows (forward levels), x = P^T L^{-T} y by columns
 // (reverse levels).  A wavefront owns one row (one column): its lanes stage 64
 // entries at a time in LDS -- the L values and the gathered right-hand-side
@@ -1129,13 +1332,61 @@ BwdSchedule backward_schedule(const kc::Plan& p) {
     return b;
 }
 
+// Groups of a supernodal plan (see ichol_group) and their units, grouped by the
+// level of the group DAG: a group waits for the groups holding its parents.
+struct GroupSchedule {
+    std::vector<kc::GroupDesc> groups;
+    std::vector<int2> units;     // (group, tile of kGroupRows panel rows)
+    std::vector<int64_t> off;    // units of each level
+};
+
+GroupSchedule group_schedule(const kc::Plan& p) {
+    GroupSchedule gs;
+    if (p.snode_ptr.empty()) return gs;
+    const int64_t n = p.n;
+    std::vector<int32_t> gid(static_cast<size_t>(n));
+    for (size_t s = 0; s + 1 < p.snode_ptr.size(); ++s) {
+        const int32_t s0 = int32_t(p.snode_ptr[s]), s1 = int32_t(p.snode_ptr[s + 1]);
+        for (int32_t g0 = s0; g0 < s1; g0 += kGroupCols) {
+            const int32_t g1 = std::min(g0 + kGroupCols, s1);
+            const int32_t nb = int32_t(p.colptr[size_t(g0) + 1] - p.colptr[size_t(g0)]) - (g1 - g0);
+            for (int32_t c = g0; c < g1; ++c) gid[size_t(c)] = int32_t(gs.groups.size());
+            gs.groups.push_back(kc::GroupDesc{g0, g1, s1, nb});
+        }
+    }
+    const size_t ng = gs.groups.size();
+    std::vector<int32_t> level(ng, 0);
+    int32_t nl = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        const int32_t g0 = gs.groups[g].g0;
+        int32_t lv = 0;
+        for (int64_t t = p.rowptr[size_t(g0)]; t < p.rowend[size_t(g0)] - 1; ++t)
+            lv = std::max(lv, level[size_t(gid[size_t(p.colidx[size_t(t)])])] + 1);
+        level[g] = lv;
+        nl = std::max(nl, lv + 1);
+    }
+    gs.off.assign(size_t(nl) + 1, 0);
+    for (size_t g = 0; g < ng; ++g) {
+        const int32_t nt = std::max(1, (gs.groups[g].nb + kGroupRows - 1) / kGroupRows);
+        gs.off[size_t(level[g]) + 1] += nt;
+    }
+    for (int32_t v = 0; v < nl; ++v) gs.off[size_t(v) + 1] += gs.off[size_t(v)];
+    gs.units.resize(size_t(gs.off[size_t(nl)]));
+    std::vector<int64_t> fill(gs.off.begin(), gs.off.end() - 1);
+    for (size_t g = 0; g < ng; ++g) {
+        const int32_t nt = std::max(1, (gs.groups[g].nb + kGroupRows - 1) / kGroupRows);
+        for (int32_t t = 0; t < nt; ++t) gs.units[size_t(fill[size_t(level[g])]++)] = int2{int32_t(g), t};
+    }
+    return gs;
+}
+
 struct Layout {
     size_t counters, xh, perm, colptr, rowidx, csc2csr, rowptr, rowend, colidx, cdelta, escptr, esc, L, Lcsc, diag,
         units, unit_off, bunits[2][3], boff[3], fwd, bshort,
-        blong, bchunks, inst, total;
+        blong, bchunks, inst, groups, gunits, total;
 };
 
-Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
+Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec, const GroupSchedule& gs = GroupSchedule()) {
     Layout o{};
     size_t at = 0;
     auto take = [&](size_t bytes) {
@@ -1174,6 +1425,8 @@ Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec) {
     o.blong = take(b.longc.size() * sizeof(kc::LongCol));
     o.bchunks = take(b.chunks.size() * sizeof(kc::BwdChunk));
     o.inst = take(p.ninst > 1 ? n * sizeof(int32_t) : 0);
+    o.groups = take(prec == KC_MIXED ? gs.groups.size() * sizeof(kc::GroupDesc) : 0);
+    o.gunits = take(prec == KC_MIXED ? gs.units.size() * sizeof(int2) : 0);
     o.total = at;
     return o;
 }
@@ -1505,6 +1758,30 @@ kc_status launch_levels(const kc_factor* f, int tn, bool cnt, double ell, const 
     }
     return KC_OK;
 }
+
+// The factorization by supernodal groups: one launch per level of the group DAG.
+template <int TN>
+kc_status launch_groups_tn(const kc_factor* f, const IcholArgs<float>& a, hipStream_t s) {
+    const size_t lds = (size_t(f->cap) + 1) * sizeof(int32_t);
+    const size_t nl = f->goff.size() - 1;
+    for (size_t v = 0; v < nl; ++v) {
+        const int64_t ub = f->goff[v], ue = f->goff[v + 1];
+        if (ue <= ub) continue;
+        ichol_group<TN><<<unsigned(ue - ub), kWave, lds, s>>>(a, f->groups, f->gunits, ub, ue);
+        KC_LAUNCH_CHECK();
+    }
+    return KC_OK;
+}
+
+kc_status launch_groups(const kc_factor* f, int tn, double ell, int pol, double tau, hipStream_t s) {
+    const IcholArgs<float> a = ichol_args<float>(f, ell, nullptr, pol, tau);
+    if (tn == 1) return launch_groups_tn<1>(f, a, s);
+    if (tn == 3) return launch_groups_tn<3>(f, a, s);
+    return launch_groups_tn<5>(f, a, s);
+}
+
+// Whether a factorization of f runs by supernodal groups (not for update counting).
+bool groups_on(const kc_factor* f, bool count) { return f->use_groups && f->groups && !count && f->prec == KC_MIXED; }
 
 // Forward sweep of levels [l0, l1): y = L^-1 P b for right-hand sides r0 .. r0+NR-1.
 template <typename VT, int NR>
@@ -1853,7 +2130,13 @@ void kc_plan_destroy(kc_plan* plan) { delete plan; }
 
 kc_status kc_factor_bytes(const kc_plan* plan, kc_prec prec, size_t* bytes) {
     if (!plan || !bytes || (prec != KC_FP64 && prec != KC_MIXED)) return KC_EINVAL;
-    *bytes = layout_of(plan->p, backward_schedule(plan->p), prec).total;
+    try {
+        *bytes = layout_of(plan->p, backward_schedule(plan->p), prec,
+                           prec == KC_MIXED ? group_schedule(plan->p) : GroupSchedule())
+                     .total;
+    } catch (const std::bad_alloc&) {
+        return KC_ENOMEM;
+    }
     return KC_OK;
 }
 
@@ -1867,12 +2150,14 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     }
     const kc::Plan& p = plan->p;
     BwdSchedule bs;
+    GroupSchedule gs;
     try {
         bs = backward_schedule(p);
+        if (prec == KC_MIXED) gs = group_schedule(p);
     } catch (const std::bad_alloc&) {
         return KC_ENOMEM;
     }
-    const Layout o = layout_of(p, bs, prec);
+    const Layout o = layout_of(p, bs, prec, gs);
     if (ws_bytes < o.total) {
         kc::set_error("kc_factor_create: workspace holds " + std::to_string(ws_bytes) + " bytes, needs " +
                       std::to_string(o.total));
@@ -1997,6 +2282,15 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
         KC_HIP(hipMemcpyAsync(f->bwd_chunks, bs.chunks.data(), bs.chunks.size() * sizeof(kc::BwdChunk),
                               hipMemcpyHostToDevice, s));
     if (f->inst) KC_HIP(hipMemcpyAsync(f->inst, p.inst.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (!gs.groups.empty()) {  // a supernodal plan in mixed precision: groups on the matrix cores by default
+        f->groups = reinterpret_cast<kc::GroupDesc*>(base + o.groups);
+        f->gunits = reinterpret_cast<int2*>(base + o.gunits);
+        f->goff = gs.off;
+        f->use_groups = true;
+        KC_HIP(hipMemcpyAsync(f->groups, gs.groups.data(), gs.groups.size() * sizeof(kc::GroupDesc),
+                              hipMemcpyHostToDevice, s));
+        KC_HIP(hipMemcpyAsync(f->gunits, gs.units.data(), gs.units.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    }
     // the sources are pageable host memory owned by the plan and bs: wait for the copies
     KC_HIP(hipStreamSynchronize(s));
     f->last = s;
@@ -2022,8 +2316,9 @@ static kc_status factorize_impl(kc_factor* f, const double* x_dev, double nu, do
     gather_points<<<grid_for(f->n * f->d, kBlock), kBlock, 0, s>>>(x_dev, f->perm, f->n, f->d, f->xh);
     KC_LAUNCH_CHECK();
     const bool cnt = count_updates != 0;
-    const kc_status st = f->prec == KC_FP64 ? launch_levels<double>(f, tn, cnt, ell, ells, int(pivot), tau, s)
-                                            : launch_levels<float>(f, tn, cnt, ell, ells, int(pivot), tau, s);
+    const kc_status st = groups_on(f, cnt) ? launch_groups(f, tn, ell, int(pivot), tau, s)
+                         : f->prec == KC_FP64 ? launch_levels<double>(f, tn, cnt, ell, ells, int(pivot), tau, s)
+                                              : launch_levels<float>(f, tn, cnt, ell, ells, int(pivot), tau, s);
     if (st != KC_OK) return st;
     f->factorized = true;
     f->counted = cnt;
@@ -2225,10 +2520,15 @@ kc_status kc_factorize_solve(kc_factor* f, const double* x_dev, kc_kernel kernel
     double* partial = reinterpret_cast<double*>(static_cast<char*>(scratch_dev) +
                                                 align256(size_t(f->n) * size_t(nrhs) * sizeof(double)));
     const double ell = ell_dev ? 0.0 : kernel.lengthscale;
-    const kc_status st =
-        f->prec == KC_FP64
-            ? factorize_solve_typed<double>(f, tn, ell, ell_dev, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s)
-            : factorize_solve_typed<float>(f, tn, ell, ell_dev, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s);
+    kc_status st;
+    if (groups_on(f, false)) {  // the group DAG has its own levels: factor, then both sweeps
+        st = launch_groups(f, tn, ell, int(pivot), tau, s);
+        if (st == KC_OK) st = solve_typed<float>(f, b_dev, x_out, nrhs, y, partial, s);
+    } else {
+        st = f->prec == KC_FP64
+                 ? factorize_solve_typed<double>(f, tn, ell, ell_dev, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s)
+                 : factorize_solve_typed<float>(f, tn, ell, ell_dev, int(pivot), tau, b_dev, x_out, nrhs, y, partial, s);
+    }
     if (st != KC_OK) return st;
     f->factorized = true;
     f->counted = false;
@@ -2483,6 +2783,16 @@ kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max,
     f->wpb = wpb;
     f->persist_max = persist_max;
     f->order = order;
+    return KC_OK;
+}
+
+kc_status kc_factor_use_groups(kc_factor* f, int32_t enable) {
+    if (!f) return KC_EINVAL;
+    if (enable && !f->groups) {
+        kc::set_error("kc_factor_use_groups: only mixed-precision factors of supernodal plans have groups");
+        return KC_EINVAL;
+    }
+    f->use_groups = enable != 0;
     return KC_OK;
 }
 

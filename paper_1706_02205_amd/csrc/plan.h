@@ -32,6 +32,13 @@ struct LongCol {
     int32_t pad;
 };
 
+// A group of at most 16 consecutive members of a supernode (supernodal plans):
+// columns [g0, g1) of the supernode that ends at s1, with nb rows below the
+// group's diagonal block in column g0.
+struct GroupDesc {
+    int32_t g0, g1, s1, nb;
+};
+
 struct Plan {
     int64_t n = 0;
     int32_t d = 0;

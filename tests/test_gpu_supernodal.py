@@ -76,6 +76,61 @@ def test_nonfinite_factor_is_counted_and_matches_oracle(K):
     assert f.stats().nonfinite == 0
 
 
+def per_column_error(colptr, L, R):
+    dL = np.abs(L - R)
+    err = np.maximum.reduceat(dL, colptr[:-1])
+    top = np.maximum.reduceat(np.abs(R), colptr[:-1])
+    return float(np.max(err / np.where(top > 0, top, 1.0)))
+
+
+@pytest.mark.parametrize("nu,d,n", [(0.5, 2, 2000), (0.5, 3, 2500), (0.5, 3, 8000)])
+def test_groups_on_matrix_cores_against_oracle(K, nu, d, n):
+    """Mixed precision on a supernodal plan factors by supernodal groups on the matrix cores (FP32
+    products on MFMA, FP64 pivots).  No bitwise bar (the FP32 sums run in another order): the factor
+    is held to the FP64 oracle per column and in Frobenius norm, and to the entry-wise mixed factor;
+    pivot decisions agree, and the solve and the fused call use it."""
+    print(f"[gpu] supernodal groups nu={nu} d={d} n={n}", flush=True)
+    x = W.uniform_points(n, d, 35)
+    Pn, sptr = O.supernodal_pattern(x, 3.0)
+    R = O.ichol(Pn, O.theta_on_pattern(Pn, nu, 0.2), O.PIVOT_SHIFT, 1e-6)
+    plan = K.analyze_supernodal(x, 3.0)
+    assert np.array_equal(plan.supernodes(), sptr)
+    big = np.diff(sptr)
+    print(f"[gpu] supernodes {len(big)}, largest {big.max()}, points in supernodes >= 16: "
+          f"{big[big >= 16].sum() / n:.2f}", flush=True)
+    if n >= 8000:
+        assert big.max() > 16  # supernodes of several groups
+    xd = dev(x)
+    fg = K.Factor(plan, "mixed")
+    fg.factorize(xd, nu, 0.2, "shift", 1e-6)
+    Lg = fg.export_L()
+    sg = fg.stats()
+    fe = K.Factor(plan, "mixed")
+    fe.use_groups(False)
+    fe.factorize(xd, nu, 0.2, "shift", 1e-6)
+    Le = fe.export_L()
+    assert sg.nonfinite == 0 and sg.shifted == fe.stats().shifted == R.shifted
+    e_or = per_column_error(Pn.colptr, Lg, R.L)
+    e_ew = per_column_error(Pn.colptr, Lg, Le)
+    e_ew_or = per_column_error(Pn.colptr, Le, R.L)
+    frob = np.linalg.norm(Lg - R.L) / np.linalg.norm(R.L)
+    print(f"[gpu] groups vs fp64 oracle: per-column {e_or:.2e} (entry-wise mixed {e_ew_or:.2e}), Frobenius {frob:.2e}; "
+          f"groups vs entry-wise mixed {e_ew:.2e}", flush=True)
+    assert e_or < 10 * e_ew_or + 1e-6 and frob < 1e-4
+    # the solve and the fused call on the grouped factor
+    b = W.gaussian_rhs(n, 3, 36)
+    x1 = fg.solve(dev(b)).cpu().numpy()
+    x2 = fg.factorize_solve(xd, dev(b), nu, 0.2, "shift", 1e-6).cpu().numpy()
+    assert np.array_equal(x1, x2) and np.array_equal(fg.export_L(), Lg)
+    ref = O.solve(Pn, R.L, b)
+    assert np.max(np.abs(x1 - ref)) / np.max(np.abs(ref)) < 1e-3
+    # update counting runs entry-wise; FP64 factors have no groups
+    fg.factorize(xd, nu, 0.2, "shift", 1e-6, count_updates=True)
+    assert fg.stats().updates == R.updates
+    with pytest.raises(K.KCholError):
+        K.Factor(plan, "fp64").use_groups(True)
+
+
 @pytest.mark.slow
 def test_uniform3d_subsample(K):
     print("[gpu] supernodal 3-D subsample", flush=True)
