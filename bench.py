@@ -287,34 +287,6 @@ def run_serving(args):
                   for r in runs]}), flush=True)
 
 
-def sampled_error(plan, points, L, nu, ell, npairs, seed):
-    """Sampled relative Frobenius error E = ||(LL^T - Theta)_pairs|| / ||Theta_pairs|| over npairs index
-    pairs drawn uniformly with replacement (the error measure of Section 4.4), from the exported
-    factor: (LL^T)_ij as sparse row dot products (scipy), Theta_ij from the closed forms (numpy exp).
-    A report of the GPU result, not a parity check."""
-    import scipy.sparse as sp
-    from paper_1706_02205_amd import workloads as W
-    perm, _, colptr, rowidx = plan.export()
-    xh = points[perm]
-    n = len(perm)
-    Lr = sp.csc_matrix((L, rowidx, colptr), shape=(n, n)).tocsr()
-    pairs = W.random_pairs(n, npairs, seed)
-    num = den = 0.0
-    for c in range(0, npairs, 20000):
-        a, b = pairs[c:c + 20000, 0], pairs[c:c + 20000, 1]
-        llt = np.asarray(Lr[a].multiply(Lr[b]).sum(axis=1)).ravel()
-        r = np.sqrt(((xh[a] - xh[b]) ** 2).sum(axis=1)) / ell
-        if nu == 0.5:
-            th = np.exp(-r)
-        elif nu == 1.5:
-            th = (1 + np.sqrt(3) * r) * np.exp(-np.sqrt(3) * r)
-        else:
-            th = (1 + np.sqrt(5) * r + 5 * r * r / 3) * np.exp(-np.sqrt(5) * r)
-        num += float(((llt - th) ** 2).sum())
-        den += float((th ** 2).sum())
-    return float(np.sqrt(num / den))
-
-
 def factor_error_report(plan, points, L64, Lmx, nu, ell, npairs=200_000, seed=1007):
     """The mixed factor against the FP64 factor at full size (the FP64 factor is the oracle's bit for bit
     wherever the oracle can run, see tests/test_gpu_fullpath_250k.py): per column max_k |dL_kj| / max_k |L_kj|
@@ -385,39 +357,101 @@ def serve_run(requests, analysis_threads, loads=(0.8,)):
     return cap, runs
 
 
+def sampled_errors(plan, points, factors, nu, ell, npairs, seed):
+    """Sampled error E of Section 4.4 for each factor (dict name -> L in CSC order) over the same pairs."""
+    import scipy.sparse as sp
+    from paper_1706_02205_amd import workloads as W
+    perm, _, colptr, rowidx = plan.export()
+    n, nnz = len(perm), int(colptr[-1])
+    idx = sp.csc_matrix((np.arange(nnz, dtype=np.float64), rowidx, colptr), shape=(n, n)).tocsr()
+    order = idx.data.astype(np.int64)
+    xh = points[perm]
+    pairs = W.random_pairs(n, npairs, seed)
+    out = {}
+    for name, L in factors.items():
+        Lr = sp.csr_matrix((L[order], idx.indices, idx.indptr), shape=(n, n))
+        num = den = 0.0
+        for c in range(0, npairs, 20000):
+            a, b = pairs[c:c + 20000, 0], pairs[c:c + 20000, 1]
+            llt = np.asarray(Lr[a].multiply(Lr[b]).sum(axis=1)).ravel()
+            r = np.sqrt(((xh[a] - xh[b]) ** 2).sum(axis=1)) / ell
+            if nu == 0.5:
+                th = np.exp(-r)
+            elif nu == 1.5:
+                th = (1 + np.sqrt(3) * r) * np.exp(-np.sqrt(3) * r)
+            else:
+                th = (1 + np.sqrt(5) * r + 5 * r * r / 3) * np.exp(-np.sqrt(5) * r)
+            num += float(((llt - th) ** 2).sum())
+            den += float((th ** 2).sum())
+        out[name] = float(np.sqrt(num / den))
+    return out
+
+
 def run_supernodal(args):
-    """N = 2e5 points iid uniform in [0,1]^3, Matern-5/2 l=0.2, rho=3: supernodal ordering and block-closed
-    pattern, mixed factorization, one solve."""
+    """N = 2e5 points iid uniform in [0,1]^3, l=0.2, rho=3 (Matern-5/2 by default, --nu 0.5 for the paper's own
+    3-D kernel): supernodal ordering and block-closed pattern, mixed factorization with SHIFT (tau = 1e-6) by
+    supernodal groups on the matrix cores (the step), beside the entry-wise factorization of the same plan
+    (with match masks when they fit in memory); counts and the sampled error E of both."""
     import torch
     import paper_1706_02205_amd as K
     from paper_1706_02205_amd import workloads as W
     w = W.uniform_3d()
+    nu = args.nu if args.nu > 0 else w.nu
+    rho = args.rho if args.rho > 0 else w.rho
     t = time.perf_counter()
-    plan = K.analyze_supernodal(w.points, w.rho, args.threads)
+    plan = K.analyze_supernodal(w.points, rho, args.threads)
     t_analysis = time.perf_counter() - t
     info = plan.info()
-    ns = len(plan.supernodes()) - 1
-    log(f"[bench] supernodal 3-D: N={w.n} nnz={info['nnz']} supernodes={ns} levels={info['nlevels']} "
-        f"analysis {t_analysis:.1f} s")
-    prec = args.prec if args.prec != "both" else "mixed"
-    # the smooth kernel leaves many nonpositive pivots at rho = 3: the paper's zeroing rule keeps L bounded
-    pivot, tau = "zero", 0.0
-    r = run_gpu(w, prec, args.steps, args.warmup, plan, pivot, tau, 0.0, keep_L=True)
-    nnz = info["nnz"]
-    tf = float(np.mean(r["t_factor"]))
+    sptr = plan.supernodes()
+    sizes = np.diff(sptr)
+    log(f"[bench] supernodal 3-D: N={w.n} nu={nu} rho={rho} nnz={info['nnz']} supernodes={len(sizes)} "
+        f"(points in supernodes >= 16: {sizes[sizes >= 16].sum() / w.n:.2f}) analysis {t_analysis:.1f} s")
+    xd = torch.from_numpy(w.points).cuda()
+    f = K.Factor(plan, "mixed")
+    pivot, tau = "shift", 1e-6
+
+    def timed(reps):
+        f.factorize(xd, nu, w.lengthscale, pivot, tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f.factorize(xd, nu, w.lengthscale, pivot, tau)
+        torch.cuda.synchronize()
+        st = f.stats()
+        return (time.perf_counter() - t0) / reps, {"shifted": st.shifted, "nonfinite": st.nonfinite}
+
+    t_groups, c_groups = timed(args.steps)
+    L_groups = f.export_L()
+    f.use_groups(False)
+    t_entry, c_entry = timed(max(1, args.steps // 3))
+    L_entry = f.export_L()
+    t_masks = None
+    if f.match_bytes() < 100e9:
+        f.build_matches()
+        t_masks, _ = timed(max(1, args.steps // 3))
+        f.drop_matches()
+    log(f"[bench] mixed factorization: groups on MFMA {t_groups * 1e3:.1f} ms, entry-wise {t_entry * 1e3:.1f} ms"
+        + (f", entry-wise with match masks {t_masks * 1e3:.1f} ms" if t_masks else "")
+        + f"; shifted {c_groups['shifted']}, non-finite {c_groups['nonfinite']} (groups) / {c_entry['nonfinite']} (entry-wise)")
+    f.use_groups(True)
     t = time.perf_counter()
-    err = sampled_error(plan, w.points, r["L"], w.nu, w.lengthscale, 200_000, 1005)
-    log(f"[bench] sampled error E of the GPU factor (200,000 pairs): {err:.3e} ({time.perf_counter() - t:.1f} s)")
+    errs = sampled_errors(plan, w.points, {"groups": L_groups, "entrywise": L_entry}, nu, w.lengthscale, 200_000, 1005)
+    log(f"[bench] sampled error E (200,000 pairs): groups {errs['groups']:.3e}, entry-wise {errs['entrywise']:.3e} "
+        f"({time.perf_counter() - t:.1f} s)")
+    nnz = info["nnz"]
+    name = f"uniform3d-n{w.n}-matern{int(round(2 * nu))}2-rho{rho:g}-supernodal"
     print(json.dumps({
-        "metric": "S-entries factored/s (supernodal pattern, 3-D)", "value": nnz * args.steps / r["wall"],
-        "unit": "S-entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": r["wall"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32-updates/f64-pivots" if prec == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "d": 3, "rho": w.rho, "supernodes": ns, "nnz": nnz,
-                   "levels": info["nlevels"], "prec": prec},
-        "factor_only": {"value": nnz / tf, "ms": tf * 1e3}, "solve_ms": float(np.mean(r["t_solve"])) * 1e3,
-        "updates": r["updates"], "nonpositive": r["nonpositive"], "rank": r["rank"],
-        "sampled_error_E": err, "sampled_error_pairs": 200_000,
+        "metric": "S-entries factored/s (supernodal pattern, 3-D, mixed)", "value": nnz / t_groups,
+        "unit": "S-entries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_groups * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-updates/f64-pivots", "data": "synthetic",
+        "config": {"workload": name, "n": w.n, "d": 3, "nu": nu, "rho": rho, "supernodes": int(len(sizes)),
+                   "max_supernode": int(sizes.max()), "points_in_supernodes_ge16": float(sizes[sizes >= 16].sum() / w.n),
+                   "nnz": nnz, "pivot": "shift 1e-6"},
+        "groups_ms": t_groups * 1e3, "entrywise_ms": t_entry * 1e3,
+        "entrywise_match_masks_ms": t_masks * 1e3 if t_masks else None,
+        "counts_groups": c_groups, "counts_entrywise": c_entry,
+        "sampled_error_E": errs, "sampled_error_pairs": 200_000,
         "host_analysis_s": t_analysis}), flush=True)
 
 
@@ -471,6 +505,8 @@ def main():
                     help="grid workload: also serve this many requests at 0.8 x measured capacity (0 = skip)")
     ap.add_argument("--error-pairs", type=int, default=200_000,
                     help="grid workload: sampled pairs for the mixed-vs-FP64 error report (0 = skip)")
+    ap.add_argument("--nu", type=float, default=0.0, help="supernodal3d: Matern smoothness (default: the workload's)")
+    ap.add_argument("--rho", type=float, default=0.0, help="supernodal3d: rho (default: the workload's)")
     ap.add_argument("--no-matches", action="store_true",
                     help="factor without match masks (index merge), e.g. to compare")
     ap.add_argument("--analysis-threads", type=int, default=12)
