@@ -4,10 +4,13 @@ Each request carries points (n x d), right-hand sides (n x nrhs) and an arrival
 time.  Its life:
 
 1. host analysis (ordering, pattern, schedule: ``kc_analyze``) on a thread pool;
-2. admission, in arrival order, as soon as an in-flight slot is free and the
-   device bytes of its factor fit in the budget next to the resident factors --
-   the budget is the nnz(S)-proportional workspace reported by
-   ``kc_factor_bytes``;
+2. admission, in the order the analyses finish, as soon as an in-flight slot is
+   free and the device bytes of its factor fit in the budget next to the
+   resident factors -- the budget is the nnz(S)-proportional workspace reported
+   by ``kc_factor_bytes``.  A request at the head that does not fit may be
+   passed by later ones that do, at most ``max_bypass`` times, after which
+   admission waits for it (so a large request is delayed boundedly, and small
+   ones do not queue behind it meanwhile);
 3. factorization and solve enqueued at once on one of several streams, so it
    runs on the device alongside requests admitted earlier (there is no batch
    boundary: a request never waits for others to finish unless the budget or
@@ -44,6 +47,7 @@ class RequestResult:
     done: float = 0.0
     solution: Optional[np.ndarray] = None
     bytes: int = 0
+    bypassed: int = 0  # times later requests were admitted before this one while it waited at the head
 
     @property
     def latency(self) -> float:
@@ -68,13 +72,15 @@ class ServeStats:
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
                 "throughput_req_s": len(self.results) / self.wall_s, "s_entries_per_s": nnz / self.wall_s,
                 "wall_s": self.wall_s, "peak_resident_bytes": self.peak_resident_bytes,
-                "peak_inflight": self.peak_inflight, "budget_bytes": self.budget_bytes}
+                "peak_inflight": self.peak_inflight, "budget_bytes": self.budget_bytes,
+                "bypasses": int(sum(r.bypassed for r in self.results)),
+                "max_bypassed": int(max(r.bypassed for r in self.results))}
 
 
 class Server:
     def __init__(self, nu: float, lengthscale: float, rho: float, prec: str = "mixed", budget_bytes: float = 64e9,
                  max_inflight: int = 8, nstreams: int = 4, analysis_threads: int = 8,
-                 analysis_nthreads: Optional[int] = None):
+                 analysis_nthreads: Optional[int] = None, max_bypass: int = 8):
         import torch
         self.nu, self.ell, self.rho, self.prec = nu, lengthscale, rho, prec
         self.pivot, self.tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
@@ -83,6 +89,9 @@ class Server:
         # that the largest requests -- the latency tail -- get the most threads
         self.analysis_nthreads = analysis_nthreads
         self.max_inflight = max_inflight
+        self.max_bypass = max_bypass
+        self._bypassed = 0      # times the current head of the ready queue has been passed
+        self._head_rid = None
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.pool = ThreadPoolExecutor(max_workers=analysis_threads)
         self._lock = threading.Lock()
@@ -119,23 +128,39 @@ class Server:
             del f
         return self._used + need <= self.budget
 
-    def _admit(self) -> bool:
-        import torch
+    def _need(self, plan, b) -> int:
         from . import _lib
         import ctypes as C
+        nb = C.c_size_t()
+        _lib.check(_lib.load().kc_factor_bytes(plan.handle, 0 if self.prec == "fp64" else 1, C.byref(nb)),
+                   "kc_factor_bytes")
+        return int(nb.value) + b.size * 8 * 4  # workspace + points/rhs/solution/scratch
+
+    def _admit(self) -> bool:
+        import torch
         with self._lock:
             if not self._ready or len(self._inflight) >= self.max_inflight:
                 return False
-            res, plan, points, b = self._ready[0]
-            nb = C.c_size_t()
-            _lib.check(_lib.load().kc_factor_bytes(plan.handle, 0 if self.prec == "fp64" else 1, C.byref(nb)),
-                       "kc_factor_bytes")
-            need = int(nb.value) + b.size * 8 * 4  # workspace + points/rhs/solution/scratch
-            if need > self.budget:
-                raise RuntimeError(f"request {res.rid} needs {need} bytes, above the whole budget {self.budget}")
-            if not self._evict_for(need):
+            head = self._ready[0][0].rid
+            if head != self._head_rid:
+                self._head_rid, self._bypassed = head, 0
+            pick = None
+            for q, (res, plan, points, b) in enumerate(self._ready):
+                need = self._need(plan, b)
+                if need > self.budget:
+                    raise RuntimeError(f"request {res.rid} needs {need} bytes, above the whole budget {self.budget}")
+                if self._evict_for(need):
+                    pick = q
+                    break
+                if q == 0 and self._bypassed >= self.max_bypass:
+                    return False  # the head has waited long enough: nothing passes it
+            if pick is None:
                 return False
-            self._ready.popleft()
+            if pick > 0:
+                self._bypassed += 1
+                self._ready[0][0].bypassed += 1
+            res, plan, points, b = self._ready[pick]
+            del self._ready[pick]
         s = self.streams[self._next_stream % len(self.streams)]
         self._next_stream += 1
         with torch.cuda.stream(s):
