@@ -1046,24 +1046,36 @@ __device__ __forceinline__ double diag_value(const VT* Lv, const double* diag, i
     else return diag[k];
 }
 
-// acc -= sum_q sL[q] * sY[q * NR + lane] for q = 0..m-1 in ascending order (the
-// sequential substitution).  LDS reads are issued eight at a time so that their
-// latency is paid once per eight dependent fmas.
-template <int NR>
+// Staging of one 64-entry chunk in LDS: sL holds the chunk's L values, sY the
+// gathered right-hand-side rows, transposed -- right-hand side r's 64 values
+// form one row of kYStride doubles.  Lane e stores entry e of every row (word
+// stride 2 between lanes: no bank conflict); lane r < NR later reads its own row
+// two entries at a time, and the rows start 4 banks apart, so those 128-bit
+// reads do not conflict either.
+constexpr int kYStride = kWave + 2;
+
+// acc -= sum_q sL[q] * sY[lane * kYStride + q] for q = 0..m-1 in ascending order
+// (the sequential substitution).  LDS reads are issued eight entries at a time,
+// as four 128-bit reads of each array, so their latency is paid once per eight
+// dependent fmas.
 __device__ __forceinline__ double apply_chunk(const double* __restrict__ sL, const double* __restrict__ sY, int m,
                                               int lane, double acc) {
+    const double* yr = sY + lane * kYStride;
     int q = 0;
     for (; q + 8 <= m; q += 8) {
-        double a[8], v[8];
+        double2 a[4], v[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            a[u] = sL[q + u];
-            v[u] = sY[(q + u) * NR + lane];
+        for (int u = 0; u < 4; ++u) {
+            a[u] = *reinterpret_cast<const double2*>(sL + q + 2 * u);
+            v[u] = *reinterpret_cast<const double2*>(yr + q + 2 * u);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = __builtin_fma(-a[u], v[u], acc);
+        for (int u = 0; u < 4; ++u) {
+            acc = __builtin_fma(-a[u].x, v[u].x, acc);
+            acc = __builtin_fma(-a[u].y, v[u].y, acc);
+        }
     }
-    for (; q < m; ++q) acc = __builtin_fma(-sL[q], sY[q * NR + lane], acc);
+    for (; q < m; ++q) acc = __builtin_fma(-sL[q], yr[q], acc);
     return acc;
 }
 
@@ -1106,10 +1118,10 @@ __device__ __forceinline__ double substitute(const int32_t* __restrict__ idx, co
             if (ci[u] >= 0) {
                 sL[lane] = lv[u];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) sY[lane * NR + r] = yv[u & 1][r];
+                for (int r = 0; r < NR; ++r) sY[r * kYStride + lane] = yv[u & 1][r];
             }
             wave_lds_sync();
-            if (lane < NR) acc = apply_chunk<NR>(sL, sY, int(b1 - c < kWave ? b1 - c : kWave), lane, acc);
+            if (lane < NR) acc = apply_chunk(sL, sY, int(b1 - c < kWave ? b1 - c : kWave), lane, acc);
             wave_lds_sync();
         }
     }
@@ -1124,8 +1136,8 @@ __global__ __launch_bounds__(kBlock) void fwd_solve(const int32_t* __restrict__ 
                                                     const double* __restrict__ diag,
                                                     const int32_t* __restrict__ perm, const double* __restrict__ b,
                                                     int ld, int r0, double* __restrict__ y) {
-    __shared__ double sL[kWavesPerBlock][kWave];
-    __shared__ double sY[kWavesPerBlock][kWave * NR];
+    __shared__ __align__(16) double sL[kWavesPerBlock][kWave];
+    __shared__ __align__(16) double sY[kWavesPerBlock][NR * kYStride];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
@@ -1149,8 +1161,8 @@ __global__ __launch_bounds__(kBlock) void bwd_solve(const int32_t* __restrict__ 
                                                     const double* __restrict__ diag,
                                                     const int32_t* __restrict__ perm, int ld, int r0,
                                                     double* __restrict__ y, double* __restrict__ x) {
-    __shared__ double sL[kWavesPerBlock][kWave];
-    __shared__ double sY[kWavesPerBlock][kWave * NR];
+    __shared__ __align__(16) double sL[kWavesPerBlock][kWave];
+    __shared__ __align__(16) double sY[kWavesPerBlock][NR * kYStride];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
