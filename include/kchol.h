@@ -194,14 +194,19 @@ kc_status kc_solve_bytes(const kc_factor *f, int32_t nrhs, size_t *bytes);
 
 /* x = P^T L^{-T} L^{-1} P b (Section 1, task (2)).  b_dev, x_dev: N x nrhs
  * row-major float64 in original order (may not alias).  A zeroed column gives
- * solution component 0.  Requires a completed kc_factorize on the same factor. */
+ * solution component 0.  Requires a completed kc_factorize on the same factor.
+ * The forward sweep and the backward sweep over short columns follow the
+ * sequential substitution (bitwise); when a column has more than 2048
+ * off-diagonal entries, the columns up to the last such one are summed in
+ * fixed pieces combined in a fixed order (deterministic, not bitwise the
+ * sequential order). */
 kc_status kc_solve(const kc_factor *f, const double *b_dev, double *x_dev, int32_t nrhs, void *scratch_dev,
                    size_t scratch_bytes, void *stream);
 
 /* kc_solve for callers that cannot allocate device memory -- code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
  * same kernels and result as kc_solve (bitwise), but its scratch (the forward
- * sweep's intermediate vector and the long columns' partial sums,
+ * sweep's intermediate vector and the backward sweep's partial sums,
  * kc_solve_bytes) lives in one fixed array of 96 MiB that the library holds on
  * each device it runs on until the process ends; no call allocates or frees
  * memory.  A solve needing more than 96 MiB of scratch (N * nrhs * 8 bytes

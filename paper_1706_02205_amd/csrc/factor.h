@@ -48,7 +48,7 @@ struct kc_factor {
     std::vector<int64_t> boff[3];
     int32_t* fwd_rows = nullptr;
     int32_t* bwd_short = nullptr;
-    kc::LongCol* bwd_long = nullptr;
+    kc::TopCol* bwd_top = nullptr;
     kc::BwdChunk* bwd_chunks = nullptr;
     int32_t* inst = nullptr;   // instance of each position (batches only)
     // supernodal groups on the matrix cores (mixed precision, supernodal plans)
@@ -58,8 +58,9 @@ struct kc_factor {
     bool use_groups = false;
     int32_t ninst = 1;
     // host schedule
-    std::vector<int64_t> unit_off, fwd_off, short_off, long_off, chunk_off;
-    int64_t max_slots = 0;    // partial sums needed by the widest reverse level
+    std::vector<int64_t> unit_off, fwd_off, short_off, top_off, tchunk_off;
+    int64_t nfine = 0;        // pieces of the top columns' rows below the top block (first in bwd_chunks)
+    int64_t max_slots = 0;    // partial sums the backward sweep needs at once
     // match masks (kc_factor_match_build), in a caller-owned buffer; null: index merge
     uint64_t* mmeta = nullptr;
     uint64_t* mwords = nullptr;

@@ -42,7 +42,9 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 wavefronts
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int64_t kLongColumn = 2048;          // backward solve: longer columns are reduced in pieces
-constexpr int64_t kChunk = 512;                // entries per partial dot product of a long column
+constexpr int64_t kChunk = 512;                // entries per partial dot product of a long top part
+constexpr int64_t kFinePiece = 2048;           // entries per piece of a top column's rows below the top block
+constexpr int64_t kBandRows = 32768;           // rows per band of those pieces (8 RHS: 2 MB of x per band)
 constexpr int kMaxRhsPerPass = 8;
 
 enum Counter {
@@ -1034,11 +1036,21 @@ __global__ __launch_bounds__(kWave) void ichol_group(IcholArgs<float> a, const k
 // (reverse levels).  A wavefront owns one row (one column): its lanes stage 64
 // entries at a time in LDS -- the L values and the gathered right-hand-side
 // rows -- and lanes r < NR then apply them to right-hand side r in ascending
-// index order, one fma each, exactly the sequential substitution.  Columns
-// longer than kLongColumn are instead cut into kChunk-entry pieces whose
-// partial dot products are reduced by whole wavefronts and added in a fixed
-// order (deterministic, but summed in a different order than the sequential
-// substitution).
+// index order, one fma each, exactly the sequential substitution.
+//
+// Long columns are the coarse ones, and each reverse level near the end holds
+// only a few of them: one launch per such level would stream their long row
+// lists level after level.  When a column is longer than kLongColumn, the
+// columns below T (T = one past the last long column: the top block) are
+// instead finished in three stages.  (1) The columns at or above T need only
+// rows at or above T, so they are solved first, by reverse level as above.
+// (2) All their x are then final, so one launch forms every top column's dot
+// product over its rows at or above T, in pieces that each stay inside one band
+// of row indices; the pieces go out band after band, so the XCD working on a
+// band finds its x rows in its L2.  (3) The top block is solved by its own
+// levels: a wavefront per column adds up the column's piece sums and its rows
+// below T in a fixed order.  Deterministic, but summed in a different order
+// than the sequential substitution.
 
 template <typename VT>
 __device__ __forceinline__ double diag_value(const VT* Lv, const double* diag, int64_t pos, int k) {
@@ -1181,7 +1193,7 @@ __global__ __launch_bounds__(kBlock) void bwd_solve(const int32_t* __restrict__ 
     }
 }
 
-// Partial dot products of long columns: one wavefront per kChunk entries.
+// Partial dot products of column pieces: one wavefront per piece.
 template <typename VT, int NR>
 __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __restrict__ chunks, int64_t beg,
                                                       int64_t end, const int64_t* __restrict__ colptr,
@@ -1194,7 +1206,7 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     if (t >= end) return;
     const kc::BwdChunk ch = chunks[t];
     const int64_t e0 = colptr[ch.col] + 1 + ch.start;
-    const int64_t e1 = e0 + kChunk < colptr[ch.col + 1] ? e0 + kChunk : colptr[ch.col + 1];
+    const int64_t e1 = e0 + ch.len;
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] = 0.0;
@@ -1233,27 +1245,60 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     }
 }
 
-// Completes the long columns of a reverse level from their partial sums: one
-// wavefront per column, lanes take every 64th piece, then a fixed butterfly.
+// Completes the top columns of one top level: a wavefront per column; its lanes
+// add the column's piece sums (lanes take every 64th) and, for a short top part,
+// its entries (every 64th, four in flight), then a fixed butterfly.
 template <typename VT, int NR>
-__global__ __launch_bounds__(kBlock) void bwd_combine(const kc::LongCol* __restrict__ lcols, int64_t beg,
-                                                      int64_t end, const int64_t* __restrict__ colptr,
-                                                      const VT* __restrict__ Lcsc, const double* __restrict__ diag,
-                                                      const int32_t* __restrict__ perm, int ld, int r0,
-                                                      const double* __restrict__ partial, double* __restrict__ y,
-                                                      double* __restrict__ x) {
+__global__ __launch_bounds__(kBlock) void bwd_finish(const kc::TopCol* __restrict__ tcols, int64_t beg, int64_t end,
+                                                     const int64_t* __restrict__ colptr,
+                                                     const int32_t* __restrict__ rowidx,
+                                                     const VT* __restrict__ Lcsc, const double* __restrict__ diag,
+                                                     const int32_t* __restrict__ perm, int ld, int r0,
+                                                     const double* __restrict__ partial, double* __restrict__ y,
+                                                     double* __restrict__ x) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
     if (t >= end) return;
-    const kc::LongCol lc = lcols[t];
+    const kc::TopCol tc = tcols[t];
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] = 0.0;
-    for (int q = lane; q < lc.nslots; q += kWave) {
-        const double* pq = partial + int64_t(lc.slot0 + q) * NR;
+    for (int q = lane; q < tc.n1; q += kWave) {
+        const double* pq = partial + int64_t(tc.s1 + q) * NR;
 #pragma unroll
         for (int r = 0; r < NR; ++r) s[r] += pq[r];
+    }
+    for (int q = lane; q < tc.n2; q += kWave) {
+        const double* pq = partial + int64_t(tc.s2 + q) * NR;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s[r] += pq[r];
+    }
+    const int64_t c0 = colptr[tc.col];
+    if (tc.n2 == 0) {
+        // rows of the top part: their columns lie in earlier top levels
+        const int64_t e1 = c0 + 1 + tc.ntop;
+        constexpr int kDepth = 4;
+        for (int64_t e = c0 + 1 + lane; e < e1; e += kDepth * kWave) {
+            double l[kDepth], v[kDepth][NR];
+#pragma unroll
+            for (int u = 0; u < kDepth; ++u) {
+                const int64_t eu = e + int64_t(u) * kWave;
+                l[u] = 0.0;
+                if (eu < e1) {
+                    l[u] = double(Lcsc[eu]);
+                    const double* xk = y + int64_t(rowidx[eu]) * ld + r0;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) v[u][r] = xk[r];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kDepth; ++u)
+                if (e + int64_t(u) * kWave < e1) {
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) s[r] = __builtin_fma(l[u], v[u][r], s[r]);
+                }
+        }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
@@ -1264,11 +1309,11 @@ __global__ __launch_bounds__(kBlock) void bwd_combine(const kc::LongCol* __restr
 #pragma unroll
         for (int r = 1; r < NR; ++r)
             if (lane == r) v = s[r];
-        const double ljj = diag_value(Lcsc, diag, colptr[lc.col], lc.col);
-        double* yj = y + int64_t(lc.col) * ld + r0 + lane;
+        const double ljj = diag_value(Lcsc, diag, c0, tc.col);
+        double* yj = y + int64_t(tc.col) * ld + r0 + lane;
         const double xv = (ljj == 0.0) ? 0.0 : (*yj - v) / ljj;
         *yj = xv;
-        x[int64_t(perm[lc.col]) * ld + r0 + lane] = xv;
+        x[int64_t(perm[tc.col]) * ld + r0 + lane] = xv;
     }
 }
 
@@ -1307,39 +1352,106 @@ namespace {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct BwdSchedule {
-    std::vector<int32_t> shortc;
-    std::vector<kc::LongCol> longc;
-    std::vector<kc::BwdChunk> chunks;
-    std::vector<int64_t> short_off, long_off, chunk_off;
+    int32_t top = 0;                      // T: one past the last long column (0: none)
+    std::vector<int32_t> shortc;          // columns >= T by reverse level
+    std::vector<int64_t> short_off;
+    std::vector<kc::BwdChunk> chunks;     // the nfine band-major pieces, then the long top parts' pieces
+    int64_t nfine = 0;
+    std::vector<kc::TopCol> topc;         // columns < T by top level
+    std::vector<int64_t> top_off, tchunk_off;
     int64_t max_slots = 0;
 };
 
-// Reverse levels split into short columns (one wavefront each) and long columns
-// (kChunk-entry pieces plus a combine step).
+// The backward sweep's schedule (see the A3 kernels): the columns at or above T
+// by reverse level; the pieces of the top columns' rows at or above T, each
+// within one band of kBandRows row indices, band after band; the top block by
+// its own levels (a column's level is one more than the highest level among the
+// rows of its top part).
 BwdSchedule backward_schedule(const kc::Plan& p) {
     BwdSchedule b;
+    const int32_t n = p.n;
+    for (int32_t j = 0; j < n; ++j)
+        if (p.colptr[j + 1] - p.colptr[j] - 1 > kLongColumn) b.top = j + 1;
+    const int32_t T = b.top;
     const int32_t nl = p.nrlevels;
     b.short_off.assign(size_t(nl + 1), 0);
-    b.long_off.assign(size_t(nl + 1), 0);
-    b.chunk_off.assign(size_t(nl + 1), 0);
     for (int32_t v = 0; v < nl; ++v) {
-        int32_t slot = 0;
         for (int64_t q = p.bwd_off[v]; q < p.bwd_off[v + 1]; ++q) {
             const int32_t j = p.bwd_cols[size_t(q)];
-            const int64_t off = p.colptr[j + 1] - p.colptr[j] - 1;  // off-diagonal entries
-            if (off <= kLongColumn) {
-                b.shortc.push_back(j);
-                continue;
-            }
-            const int32_t pieces = int32_t((off + kChunk - 1) / kChunk);
-            b.longc.push_back(kc::LongCol{j, slot, pieces, 0});
-            for (int32_t c = 0; c < pieces; ++c) b.chunks.push_back(kc::BwdChunk{j, int32_t(c * kChunk), slot + c, 0});
-            slot += pieces;
+            if (j >= T) b.shortc.push_back(j);
         }
-        b.max_slots = std::max<int64_t>(b.max_slots, slot);
         b.short_off[v + 1] = int64_t(b.shortc.size());
-        b.long_off[v + 1] = int64_t(b.longc.size());
-        b.chunk_off[v + 1] = int64_t(b.chunks.size());
+    }
+    if (T == 0) return b;
+    // split of each top column: entries [c0 + 1, fb) have rows < T, [fb, c1) rows >= T
+    std::vector<int64_t> fb(static_cast<size_t>(T));
+    for (int32_t j = 0; j < T; ++j)
+        fb[size_t(j)] = std::lower_bound(p.rowidx.begin() + p.colptr[j] + 1, p.rowidx.begin() + p.colptr[j + 1], T) -
+                        p.rowidx.begin();
+    // pieces of the rows >= T: slots column by column, pieces band after band
+    const int64_t nfine_rows = int64_t(n) - T;
+    const int64_t nb = std::min<int64_t>(64, std::max<int64_t>(1, (nfine_rows + kBandRows - 1) / kBandRows));
+    const int64_t width = (nfine_rows + nb - 1) / nb;
+    std::vector<std::vector<kc::BwdChunk>> band(static_cast<size_t>(nb));
+    std::vector<int32_t> s1(static_cast<size_t>(T)), n1(static_cast<size_t>(T));
+    int64_t slot = 0;
+    for (int32_t j = 0; j < T; ++j) {
+        const int64_t c0 = p.colptr[j], c1 = p.colptr[j + 1];
+        s1[size_t(j)] = int32_t(slot);
+        int64_t pos = fb[size_t(j)];
+        for (int64_t q = 0; q < nb && pos < c1; ++q) {
+            const int64_t bound = std::min<int64_t>(int64_t(n), T + (q + 1) * width);
+            const int64_t hi = std::lower_bound(p.rowidx.begin() + pos, p.rowidx.begin() + c1, int32_t(bound)) -
+                               p.rowidx.begin();
+            for (int64_t e = pos; e < hi; e += kFinePiece) {
+                const int64_t len = std::min<int64_t>(kFinePiece, hi - e);
+                band[size_t(q)].push_back(kc::BwdChunk{j, int32_t(e - c0 - 1), int32_t(slot++), int32_t(len)});
+            }
+            pos = hi;
+        }
+        n1[size_t(j)] = int32_t(slot - s1[size_t(j)]);
+    }
+    for (auto& bq : band) b.chunks.insert(b.chunks.end(), bq.begin(), bq.end());
+    b.nfine = int64_t(b.chunks.size());
+    const int64_t fine_slots = slot;
+    b.max_slots = fine_slots;
+    // levels of the top block
+    std::vector<int32_t> rt(static_cast<size_t>(T), 0);
+    int32_t ntl = 0;
+    for (int32_t j = T - 1; j >= 0; --j) {
+        int32_t m = -1;
+        for (int64_t e = p.colptr[j] + 1; e < fb[size_t(j)]; ++e) m = std::max(m, rt[size_t(p.rowidx[e])]);
+        rt[size_t(j)] = m + 1;
+        ntl = std::max(ntl, m + 2);
+    }
+    std::vector<int64_t> cnt(size_t(ntl) + 1, 0);
+    for (int32_t j = 0; j < T; ++j) ++cnt[size_t(rt[size_t(j)]) + 1];
+    for (int32_t v = 0; v < ntl; ++v) cnt[size_t(v) + 1] += cnt[size_t(v)];
+    std::vector<int32_t> bylevel(static_cast<size_t>(T));
+    {
+        std::vector<int64_t> at(cnt.begin(), cnt.end() - 1);
+        for (int32_t j = 0; j < T; ++j) bylevel[size_t(at[size_t(rt[size_t(j)])]++)] = j;
+    }
+    b.top_off.assign(size_t(ntl) + 1, 0);
+    b.tchunk_off.assign(size_t(ntl) + 1, 0);
+    for (int32_t v = 0; v < ntl; ++v) {
+        int64_t lslot = fine_slots;
+        for (int64_t q = cnt[size_t(v)]; q < cnt[size_t(v) + 1]; ++q) {
+            const int32_t j = bylevel[size_t(q)];
+            const int64_t ntop = fb[size_t(j)] - p.colptr[j] - 1;
+            kc::TopCol tc{j, s1[size_t(j)], n1[size_t(j)], 0, 0, int32_t(ntop), 0, 0};
+            if (ntop > kLongColumn) {
+                tc.s2 = int32_t(lslot);
+                for (int64_t e = 0; e < ntop; e += kChunk)
+                    b.chunks.push_back(
+                        kc::BwdChunk{j, int32_t(e), int32_t(lslot++), int32_t(std::min<int64_t>(kChunk, ntop - e))});
+                tc.n2 = int32_t(lslot - tc.s2);
+            }
+            b.topc.push_back(tc);
+        }
+        b.max_slots = std::max(b.max_slots, lslot);
+        b.top_off[size_t(v) + 1] = int64_t(b.topc.size());
+        b.tchunk_off[size_t(v) + 1] = int64_t(b.chunks.size()) - b.nfine;
     }
     return b;
 }
@@ -1434,7 +1546,7 @@ Layout layout_of(const kc::Plan& p, const BwdSchedule& b, kc_prec prec, const Gr
     }
     o.fwd = take(n * sizeof(int32_t));
     o.bshort = take(b.shortc.size() * sizeof(int32_t));
-    o.blong = take(b.longc.size() * sizeof(kc::LongCol));
+    o.blong = take(b.topc.size() * sizeof(kc::TopCol));
     o.bchunks = take(b.chunks.size() * sizeof(kc::BwdChunk));
     o.inst = take(p.ninst > 1 ? n * sizeof(int32_t) : 0);
     o.groups = take(prec == KC_MIXED ? gs.groups.size() * sizeof(kc::GroupDesc) : 0);
@@ -1822,14 +1934,25 @@ kc_status bwd_levels(const kc_factor* f, double* x, int ld, int r0, double* y, d
                 f->bwd_short, sb, se, f->colptr, f->rowidx, Lc, f->diag, f->perm, ld, r0, y, x);
             KC_LAUNCH_CHECK();
         }
-        const int64_t cb = f->chunk_off[v], ce = f->chunk_off[v + 1];
+    }
+    if (f->top_off.empty()) return KC_OK;
+    if (f->nfine > 0) {
+        bwd_partial<VT, NR><<<grid_for(f->nfine, kWavesPerBlock), kBlock, 0, s>>>(
+            f->bwd_chunks, 0, f->nfine, f->colptr, f->rowidx, Lc, ld, r0, y, partial);
+        KC_LAUNCH_CHECK();
+    }
+    const size_t nt = f->top_off.size() - 1;
+    for (size_t v = 0; v < nt; ++v) {
+        const int64_t cb = f->nfine + f->tchunk_off[v], ce = f->nfine + f->tchunk_off[v + 1];
         if (ce > cb) {
             bwd_partial<VT, NR><<<grid_for(ce - cb, kWavesPerBlock), kBlock, 0, s>>>(
                 f->bwd_chunks, cb, ce, f->colptr, f->rowidx, Lc, ld, r0, y, partial);
             KC_LAUNCH_CHECK();
-            const int64_t lb = f->long_off[v], le = f->long_off[v + 1];
-            bwd_combine<VT, NR><<<grid_for(le - lb, kWavesPerBlock), kBlock, 0, s>>>(f->bwd_long, lb, le, f->colptr, Lc,
-                                                                            f->diag, f->perm, ld, r0, partial, y, x);
+        }
+        const int64_t tb = f->top_off[v], te = f->top_off[v + 1];
+        if (te > tb) {
+            bwd_finish<VT, NR><<<grid_for(te - tb, kWavesPerBlock), kBlock, 0, s>>>(
+                f->bwd_top, tb, te, f->colptr, f->rowidx, Lc, f->diag, f->perm, ld, r0, partial, y, x);
             KC_LAUNCH_CHECK();
         }
     }
@@ -2230,15 +2353,16 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     }
     f->fwd_rows = reinterpret_cast<int32_t*>(base + o.fwd);
     f->bwd_short = reinterpret_cast<int32_t*>(base + o.bshort);
-    f->bwd_long = reinterpret_cast<kc::LongCol*>(base + o.blong);
+    f->bwd_top = reinterpret_cast<kc::TopCol*>(base + o.blong);
     f->bwd_chunks = reinterpret_cast<kc::BwdChunk*>(base + o.bchunks);
     f->inst = p.ninst > 1 ? reinterpret_cast<int32_t*>(base + o.inst) : nullptr;
     f->ninst = p.ninst;
     f->unit_off = p.unit_off;
     f->fwd_off = p.fwd_off;
     f->short_off = bs.short_off;
-    f->long_off = bs.long_off;
-    f->chunk_off = bs.chunk_off;
+    f->top_off = bs.top_off;
+    f->tchunk_off = bs.tchunk_off;
+    f->nfine = bs.nfine;
     f->max_slots = bs.max_slots;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -2287,8 +2411,8 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     if (!bs.shortc.empty())
         KC_HIP(hipMemcpyAsync(f->bwd_short, bs.shortc.data(), bs.shortc.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, s));
-    if (!bs.longc.empty())
-        KC_HIP(hipMemcpyAsync(f->bwd_long, bs.longc.data(), bs.longc.size() * sizeof(kc::LongCol),
+    if (!bs.topc.empty())
+        KC_HIP(hipMemcpyAsync(f->bwd_top, bs.topc.data(), bs.topc.size() * sizeof(kc::TopCol),
                               hipMemcpyHostToDevice, s));
     if (!bs.chunks.empty())
         KC_HIP(hipMemcpyAsync(f->bwd_chunks, bs.chunks.data(), bs.chunks.size() * sizeof(kc::BwdChunk),

@@ -17,19 +17,22 @@ struct Unit {
 
 constexpr int kRowAlign = 64;
 
-// Backward solve of a long column: one piece of its dot product ...
+// Backward solve: one piece of a column's dot product sum_k L_kj x_k over
+// entries [start, start + len) counted from the diagonal's successor ...
 struct BwdChunk {
     int32_t col;    // column j
-    int32_t start;  // first off-diagonal entry of the piece, counted from the diagonal's successor
-    int32_t slot;   // where the piece's partial sums go (per reverse level)
-    int32_t pad;
+    int32_t start;
+    int32_t slot;   // where the piece's partial sums go
+    int32_t len;
 };
-// ... and the column that combines its pieces' partial sums.
-struct LongCol {
+// ... and a column of the top block (the columns up to the last long one),
+// finished from its pieces' partial sums and its top part.
+struct TopCol {
     int32_t col;
-    int32_t slot0;
-    int32_t nslots;
-    int32_t pad;
+    int32_t s1, n1;  // partial sums of its rows below the top block
+    int32_t s2, n2;  // partial sums of a long top part (n2 = 0: the part is summed in place)
+    int32_t ntop;    // entries of the top part: rows above the diagonal's successor and below the top bound
+    int32_t pad0, pad1;
 };
 
 // A group of at most 16 consecutive members of a supernode (supernodal plans):
