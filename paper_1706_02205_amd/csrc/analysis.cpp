@@ -6,7 +6,10 @@
 // current distances, but the candidate points to update are found with a k-d
 // tree search around the newly selected point instead of parent/child lists:
 // a subtree is entered only if its box may hold an unselected point closer than
-// that point's current distance (per-node upper bounds of those distances).  Every comparison that decides the output uses the same
+// that point's current distance (per-node upper bounds of those distances).
+// From kParallelOrderMin points on, the ordering takes batches of heap
+// candidates at once and applies their updates on several threads; the output
+// is the same (see maximin_parallel).  Every comparison that decides the output uses the same
 // floating-point expression as the definition, so the result is exactly the
 // greedy maximin ordering and exactly S_rho:
 //   dist(a,b) = sqrt(sum_t (a_t - b_t)^2), summed over t ascending, no fma;
@@ -195,6 +198,8 @@ struct KDTree {
 // a level of a sift reads one 64-byte group of children instead of chasing ids
 // into the key array (a cache miss per comparison on large inputs).  The order
 // is strict and total, so the sequence of pops is that of any correct heap.
+// pos[slot] (caller-owned) locates a slot's entry; heaps over disjoint slot sets
+// may share one pos array.
 struct MaxHeap {
     struct Entry {
         double key;
@@ -203,21 +208,21 @@ struct MaxHeap {
     };
     std::vector<Entry> store;
     Entry* h = nullptr;  // h[0] is the root; children of i are 4i+1 .. 4i+4
-    std::vector<int32_t> pos;
+    int32_t* pos = nullptr;
     int64_t size = 0;
 
     static bool greater(const Entry& a, const Entry& b) { return a.key > b.key || (a.key == b.key && a.id < b.id); }
-    // entry s has key[s], original index id[s] and slot s
-    void init(int64_t n, const double* key, const int32_t* id) {
+    void init(const std::vector<Entry>& entries, int32_t* posv) {
+        const int64_t n = int64_t(entries.size());
         // element 1 on a 64-byte boundary, so every group of 4 children shares one line
         store.resize(size_t(n) + 8);
         const uintptr_t base = reinterpret_cast<uintptr_t>(store.data());
         const uintptr_t want = ((base + 16 + 63) & ~uintptr_t(63)) - 16;
         h = reinterpret_cast<Entry*>(want);
-        pos.resize(size_t(n));
+        pos = posv;
         for (int64_t i = 0; i < n; ++i) {
-            h[i] = Entry{key[i], id[i], int32_t(i)};
-            pos[size_t(i)] = int32_t(i);
+            h[i] = entries[size_t(i)];
+            pos[size_t(h[i].slot)] = int32_t(i);
         }
         size = n;
         for (int64_t i = (n - 2) / 4; i >= 0; --i) sift_down(i);
@@ -235,6 +240,18 @@ struct MaxHeap {
             h[i] = h[best];
             pos[size_t(h[i].slot)] = int32_t(i);
             i = best;
+        }
+        h[i] = v;
+        pos[size_t(v.slot)] = int32_t(i);
+    }
+    void sift_up(int64_t i) {
+        const Entry v = h[i];
+        while (i > 0) {
+            const int64_t up = (i - 1) / 4;
+            if (!greater(v, h[up])) break;
+            h[i] = h[up];
+            pos[size_t(h[i].slot)] = int32_t(i);
+            i = up;
         }
         h[i] = v;
         pos[size_t(v.slot)] = int32_t(i);
@@ -257,12 +274,173 @@ struct MaxHeap {
         pos[size_t(top)] = -1;
         return top;
     }
+    // puts back an entry popped from this heap
+    void push(const Entry& e) {
+        h[size] = e;
+        sift_up(size++);
+    }
 };
+
+// Reusable barrier for a fixed team of threads: spins briefly, then yields.
+class SpinBarrier {
+public:
+    explicit SpinBarrier(int n) : n_(n) {}
+    void wait() {
+        const int g = gen_.load(std::memory_order_acquire);
+        if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
+            count_.store(0, std::memory_order_relaxed);
+            gen_.fetch_add(1, std::memory_order_release);
+            return;
+        }
+        for (int spins = 0; gen_.load(std::memory_order_acquire) == g; ++spins)
+            if (spins > 4096) std::this_thread::yield();
+    }
+
+private:
+    int n_;
+    std::atomic<int> count_{0};
+    std::atomic<int> gen_{0};
+};
+
+// Below this size the ordering runs on one thread.
+constexpr int64_t kParallelOrderMin = 16384;
+
+// The exact greedy maximin ordering on several threads: the same output as the
+// one-thread loop in maximin_order, by this argument.  Candidates leave the
+// heaps in the one-thread pop order (current distance m descending, index
+// ascending).  The first is the next point.  A later candidate c is the next
+// point after the candidates already taken in the batch if no taken point a has
+// dist(a, c) < m[c]: c's distance is then unchanged by them, every other
+// point's distance only fell, so c still leads that order.  The first
+// candidate that fails ends the batch and, with those after it, returns to its
+// heap.  A batch's updates m[j] = min(m[j], dist(x_j, x_a)) commute, so the
+// threads apply them at once, each to the points of the k-d subtrees it owns
+// (with its own heap over them), and the comparisons that decide the output
+// are those of the one-thread loop.
+void maximin_parallel(const KDTree& tree, const std::vector<double>& xt, int64_t n, int32_t d, int nthreads,
+                      int32_t* perm, double* l) {
+    const int P = nthreads;
+    // subtrees to share out: a frontier of at least 8 per thread
+    std::vector<int32_t> parts{0};
+    for (bool grew = true; grew && int64_t(parts.size()) < 8 * int64_t(P);) {
+        grew = false;
+        std::vector<int32_t> next;
+        for (int32_t q : parts) {
+            const auto& nd = tree.nodes[size_t(q)];
+            if (nd.left >= 0) {
+                next.push_back(nd.left);
+                next.push_back(nd.right);
+                grew = true;
+            } else {
+                next.push_back(q);
+            }
+        }
+        parts.swap(next);
+    }
+    std::vector<std::vector<int32_t>> mine(static_cast<size_t>(P));
+    for (size_t q = 0; q < parts.size(); ++q) mine[q % size_t(P)].push_back(parts[q]);
+    std::vector<double> m(size_t(n), std::numeric_limits<double>::infinity());
+    std::vector<char> sel(size_t(n), 0);
+    std::vector<int32_t> pos(size_t(n), -1);
+    std::vector<MaxHeap> heaps(static_cast<size_t>(P));
+    for (int t = 0; t < P; ++t) {
+        std::vector<MaxHeap::Entry> e;
+        for (int32_t q : mine[size_t(t)])
+            for (int32_t s = tree.nodes[size_t(q)].begin; s < tree.nodes[size_t(q)].end; ++s)
+                e.push_back(MaxHeap::Entry{std::numeric_limits<double>::infinity(), tree.idx[size_t(s)], s});
+        heaps[size_t(t)].init(e, pos.data());
+    }
+    std::vector<double> ub(tree.nodes.size(), std::numeric_limits<double>::infinity());
+
+    std::vector<MaxHeap::Entry> cand;
+    std::vector<int32_t> owner;
+    std::vector<int32_t> taken;
+    std::atomic<int64_t> conflict{0};
+    int64_t k = 0, batch = 16;
+    bool done = false;
+    SpinBarrier bar(P);
+    auto team = [&](int t) {
+        MaxHeap& heap = heaps[size_t(t)];
+        const double* xi = nullptr;
+        auto leaf_update = [&](int32_t b, int32_t e) {
+            double u = -std::numeric_limits<double>::infinity();
+            for (int32_t s = b; s < e; ++s) {
+                if (sel[size_t(s)]) continue;
+                const double dj = dist(xt.data() + size_t(s) * d, xi, d);
+                if (dj < m[size_t(s)]) {
+                    m[size_t(s)] = dj;
+                    heap.decrease(s, dj);
+                }
+                u = std::max(u, m[size_t(s)]);
+            }
+            return u;
+        };
+        for (;;) {
+            if (t == 0) {  // the next candidates, in pop order
+                cand.clear();
+                owner.clear();
+                while (int64_t(cand.size()) < batch) {
+                    int best = -1;
+                    for (int q = 0; q < P; ++q)
+                        if (heaps[size_t(q)].size > 0 &&
+                            (best < 0 || MaxHeap::greater(heaps[size_t(q)].h[0], heaps[size_t(best)].h[0])))
+                            best = q;
+                    if (best < 0) break;
+                    cand.push_back(heaps[size_t(best)].h[0]);
+                    owner.push_back(best);
+                    heaps[size_t(best)].pop();
+                }
+                done = cand.empty();
+                conflict.store(int64_t(cand.size()), std::memory_order_relaxed);
+            }
+            bar.wait();
+            if (done) break;
+            // first candidate within its own distance of an earlier one
+            const int64_t nc = int64_t(cand.size());
+            for (int64_t j = 1 + t; j < nc; j += P) {
+                if (j >= conflict.load(std::memory_order_relaxed)) break;
+                const double* xj = xt.data() + size_t(cand[size_t(j)].slot) * d;
+                for (int64_t i = 0; i < j; ++i)
+                    if (dist(xt.data() + size_t(cand[size_t(i)].slot) * d, xj, d) < cand[size_t(j)].key) {
+                        int64_t cur = conflict.load(std::memory_order_relaxed);
+                        while (j < cur && !conflict.compare_exchange_weak(cur, j, std::memory_order_relaxed)) {
+                        }
+                        break;
+                    }
+            }
+            bar.wait();
+            if (t == 0) {
+                const int64_t J = conflict.load(std::memory_order_relaxed);
+                taken.clear();
+                for (int64_t i = 0; i < J; ++i) {
+                    const int32_t s = cand[size_t(i)].slot;
+                    perm[k] = tree.idx[size_t(s)];
+                    l[k] = cand[size_t(i)].key;
+                    ++k;
+                    sel[size_t(s)] = 1;
+                    taken.push_back(s);
+                }
+                for (int64_t i = J; i < nc; ++i) heaps[size_t(owner[size_t(i)])].push(cand[size_t(i)]);
+                batch = std::min<int64_t>(512, std::max<int64_t>(16, 2 * J + 16));
+            }
+            bar.wait();
+            // the batch's updates, on this thread's subtrees
+            for (int32_t s : taken) {
+                xi = xt.data() + size_t(s) * d;
+                for (int32_t q : mine[size_t(t)]) tree.relax(q, xi, ub, leaf_update);
+            }
+            bar.wait();
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < P; ++t) pool.emplace_back(team, t);
+    team(0);
+    for (auto& th : pool) th.join();
+}
 
 }  // namespace
 
 void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t* perm, double* l) {
-    (void)nthreads;
     KDTree tree;
     tree.build(x, n, d);
     // The working arrays are laid out in tree order (slot t holds point tree.idx[t]),
@@ -270,10 +448,20 @@ void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t*
     std::vector<double> xt(size_t(n) * d);
     for (int64_t t = 0; t < n; ++t)
         std::copy(x + size_t(tree.idx[t]) * d, x + size_t(tree.idx[t] + 1) * d, xt.begin() + size_t(t) * d);
+    nthreads = resolve_threads(nthreads);
+    if (nthreads > 1 && n >= kParallelOrderMin) {
+        maximin_parallel(tree, xt, n, d, std::min(nthreads, 64), perm, l);
+        return;
+    }
     std::vector<double> m(static_cast<size_t>(n), std::numeric_limits<double>::infinity());
     std::vector<char> sel(static_cast<size_t>(n), 0);
+    std::vector<int32_t> pos(static_cast<size_t>(n), -1);
     MaxHeap heap;
-    heap.init(n, m.data(), tree.idx.data());
+    {
+        std::vector<MaxHeap::Entry> e(static_cast<size_t>(n));
+        for (int64_t t = 0; t < n; ++t) e[size_t(t)] = MaxHeap::Entry{m[size_t(t)], tree.idx[size_t(t)], int32_t(t)};
+        heap.init(e, pos.data());
+    }
     std::vector<double> ub(tree.nodes.size(), std::numeric_limits<double>::infinity());
     const double* xi = nullptr;
     auto leaf_update = [&](int32_t b, int32_t e) {

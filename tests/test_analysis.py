@@ -41,6 +41,27 @@ def test_ties_and_duplicates():
     assert_same(x, 2.5, "min")
 
 
+@pytest.mark.parametrize("name", ["grid2d", "sincos20d", "lattice", "duplicates"])
+def test_ordering_on_several_threads_matches_oracle(name):
+    """From 16,384 points on, the ordering runs in batches on several threads; it must still be
+    the oracle's greedy maximin ordering bit for bit, ties and duplicates included."""
+    if name == "grid2d":
+        x = W.jittered_grid(140, 21)
+    elif name == "sincos20d":
+        x = W.embedded_sincos(17000, 22)
+    elif name == "lattice":
+        x = np.array([(a, b) for a in range(130) for b in range(130)], dtype=np.float64)
+    else:
+        base = W.uniform_points(9000, 2, 23)
+        x = np.concatenate([base, base[:8000], base[:500]])
+    assert len(x) >= 16384
+    perm, l = O.maximin(x)
+    for nthreads in (2, 8):
+        pp, ll, _, _ = K.analyze(x, 3.0, "max", nthreads).export()
+        np.testing.assert_array_equal(pp, perm)
+        np.testing.assert_array_equal(ll, l)
+
+
 def test_tiny_inputs():
     for n in (1, 2, 3):
         assert_same(W.uniform_points(n, 2, 12), 2.0, "max")
