@@ -301,6 +301,17 @@ kc_status kc_factor_schedule(const kc_factor *f, int32_t *wpb, int64_t *persist_
  * FP32 rounding order).  KC_EINVAL when enabling on a factor without groups. */
 kc_status kc_factor_use_groups(kc_factor *f, int32_t enable);
 
+/* Rows of S with more than max_parents parents are not staged in LDS: the
+ * factorization's wavefronts read such a row's indices and values from device
+ * memory (the same merge, the same updates in the same order of Section 2.2's
+ * algorithm, so the same L; slower).  Rows that do not fit in LDS take that
+ * path anyway, so no pattern is refused for its row lengths; a factor starts
+ * with the largest limit the LDS allows, and max_parents = -1 restores it.
+ * Supernodal groups and match masks need every row staged: with a longer row
+ * the factorization is entry-wise and kc_factor_match_build returns KC_ERANGE;
+ * lowering the limit under attached masks returns KC_EINVAL. */
+kc_status kc_factor_set_stage_limit(kc_factor *f, int32_t max_parents);
+
 /* Autotuner: times the factorization (reps repetitions after a warm-up) for
  * every schedule in {1, 2, 4} wavefronts per workgroup x level grouping
  * persist_max in {0, 256, 4096, all levels} x unit order {SPATIAL, LONGEST} --

@@ -246,6 +246,11 @@ class Factor:
         such factors) or entry by entry (enable=False)."""
         _lib.check(_lib.load().kc_factor_use_groups(self._h, int(bool(enable))), "kc_factor_use_groups")
 
+    def set_stage_limit(self, max_parents: int = -1) -> None:
+        """Rows with more than max_parents parents are read from device memory instead of staged in LDS
+        (the same L); -1 restores the largest limit the LDS allows."""
+        _lib.check(_lib.load().kc_factor_set_stage_limit(self._h, int(max_parents)), "kc_factor_set_stage_limit")
+
     def schedule(self) -> tuple:
         """(wavefronts per workgroup, persist_max, unit order) in use -- the tuner's choice after tune()."""
         w, pm, o = C.c_int32(), C.c_int64(), C.c_int()

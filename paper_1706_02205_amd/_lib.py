@@ -44,7 +44,7 @@ EXPORTED = ("kc_status_string", "kc_last_error", "kc_analyze", "kc_plan_info", "
             "kc_dense_matvec", "kc_pcg_bytes", "kc_pcg", "kc_analyze_batched", "kc_factorize_batched",
             "kc_factor_tune", "kc_factor_set_schedule", "kc_factor_schedule", "kc_graph_create", "kc_graph_info", "kc_graph_launch", "kc_graph_destroy", "kc_analyze_supernodal",
             "kc_plan_supernodes", "kc_solve_noalloc", "kc_factor_match_bytes", "kc_factor_match_build",
-            "kc_factor_use_groups")
+            "kc_factor_use_groups", "kc_factor_set_stage_limit")
 
 _LIB = None
 
@@ -105,6 +105,7 @@ def load():
         "kc_factor_match_bytes": (C.c_int, [vp, vp, P(sz)]),
         "kc_factor_match_build": (C.c_int, [vp, vp, sz, vp]),
         "kc_factor_use_groups": (C.c_int, [vp, i32]),
+        "kc_factor_set_stage_limit": (C.c_int, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -24,6 +24,8 @@
 #include <chrono>
 #include <cmath>
 #include <climits>
+#include <condition_variable>
+#include <mutex>
 #include <limits>
 #include <thread>
 #include <vector>
@@ -281,29 +283,45 @@ struct MaxHeap {
     }
 };
 
-// Reusable barrier for a fixed team of threads: spins briefly, then yields.
-class SpinBarrier {
+// Reusable barrier for a fixed team of threads: spins briefly, then sleeps, so
+// that teams of concurrent analyses (a server's) do not burn each other's cores.
+class TeamBarrier {
+    static constexpr int kSpins = 1 << 15;  // about 0.1-0.3 ms of pauses: longer than a batch phase
+
 public:
-    explicit SpinBarrier(int n) : n_(n) {}
+    explicit TeamBarrier(int n) : n_(n) {}
     void wait() {
         const int g = gen_.load(std::memory_order_acquire);
         if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
             count_.store(0, std::memory_order_relaxed);
-            gen_.fetch_add(1, std::memory_order_release);
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                gen_.fetch_add(1, std::memory_order_release);
+            }
+            cv_.notify_all();
             return;
         }
-        for (int spins = 0; gen_.load(std::memory_order_acquire) == g; ++spins)
-            if (spins > 4096) std::this_thread::yield();
+        for (int spins = 0; spins < kSpins; ++spins) {
+            if (gen_.load(std::memory_order_acquire) != g) return;
+            __builtin_ia32_pause();
+        }
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != g; });
     }
 
 private:
     int n_;
     std::atomic<int> count_{0};
     std::atomic<int> gen_{0};
+    std::mutex mu_;
+    std::condition_variable cv_;
 };
 
-// Below this size the ordering runs on one thread.
+// Below this size the ordering runs on one thread; above, on at most
+// kOrderThreads (a batch waits for its slowest thread four times, so more
+// threads gain little and lose much when other work shares the cores).
 constexpr int64_t kParallelOrderMin = 16384;
+constexpr int kOrderThreads = 4;
 
 // The exact greedy maximin ordering on several threads: the same output as the
 // one-thread loop in maximin_order, by this argument.  Candidates leave the
@@ -358,7 +376,7 @@ void maximin_parallel(const KDTree& tree, const std::vector<double>& xt, int64_t
     std::atomic<int64_t> conflict{0};
     int64_t k = 0, batch = 16;
     bool done = false;
-    SpinBarrier bar(P);
+    TeamBarrier bar(P);
     auto team = [&](int t) {
         MaxHeap& heap = heaps[size_t(t)];
         const double* xi = nullptr;
@@ -450,7 +468,7 @@ void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t*
         std::copy(x + size_t(tree.idx[t]) * d, x + size_t(tree.idx[t] + 1) * d, xt.begin() + size_t(t) * d);
     nthreads = resolve_threads(nthreads);
     if (nthreads > 1 && n >= kParallelOrderMin) {
-        maximin_parallel(tree, xt, n, d, std::min(nthreads, 64), perm, l);
+        maximin_parallel(tree, xt, n, d, std::min(nthreads, kOrderThreads), perm, l);
         return;
     }
     std::vector<double> m(static_cast<size_t>(n), std::numeric_limits<double>::infinity());

@@ -14,6 +14,8 @@ struct kc_factor {
     int32_t d = 0;
     int32_t cap = 0;          // LDS entries of the staged row (longest row + 2, rounded up)
     int32_t nbuck = 0;        // bucket directory of the staged row (0: cursor merge)
+    int32_t max_row = 0;      // longest row of S (parents)
+    int32_t stage_max = 0;    // rows with more parents are not staged in LDS (read from device memory)
     int32_t wpb = 4;          // wavefronts per block of the factorization kernel
     int64_t persist_max = 0;  // levels with at most this many units run in persistent launches
     int32_t num_cu = 0;       // compute units of the factor's device

@@ -234,6 +234,7 @@ struct IcholArgs {
     int policy;
     double tau;
     int cap;
+    int stage_max;  // rows with more parents are read from device memory, not staged
     int nbuck;  // 0: cursor merge; else buckets of the staged row's directory (a power of 2)
     unsigned long long* counters;
     // match masks (see match_masks_kernel), or null: per CSC entry a word offset and
@@ -747,6 +748,25 @@ __device__ __forceinline__ void factor_entries_mask(const IcholArgs<VT>& a, int 
     if (hard && active) atomicAdd(counters + kExpHard, 1ull);
 }
 
+// A row j with more parents than a.stage_max (at most a.cap - 2: what the LDS
+// holds beside the sentinel) is not staged: its wavefronts read row j's indices
+// and values from device memory, where the diagonal entry, index j, ends every
+// cursor walk as the sentinel does in LDS -- the same merge, the same updates
+// in the same order, so the same L.
+template <typename VT>
+__device__ __forceinline__ bool row_unstaged(const IcholArgs<VT>& a, int j) {
+    return a.rowend[j] - 1 - a.rowptr[j] > a.stage_max;
+}
+
+template <int TWONU, bool COUNT, typename VT, bool MASK>
+__device__ __forceinline__ void factor_unstaged(const IcholArgs<VT>& a, int j, int first, int lane) {
+    const int64_t t0 = a.rowptr[j];
+    const int np = int(a.rowend[j] - 1 - t0);
+    if (a.colptr[j] + first >= a.colptr[j + 1]) return;
+    if constexpr (MASK) factor_entries_mask<TWONU, COUNT, VT>(a, j, first, np, lane, a.Lv + t0);
+    else factor_entries<TWONU, COUNT, VT, false>(a, j, first, np, lane, a.Lv + t0, a.colidx + t0, nullptr, 0);
+}
+
 // One DAG level per launch.  A workgroup owns a block unit: 64 * WPB consecutive
 // entries of one column, 64 per wave, with the column's row staged once in LDS.
 // MASK: the factorization with match masks (factor_entries_mask; only the
@@ -764,6 +784,10 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_level(IcholArgs<VT> a, cons
     if (bu >= uend) return;  // the whole workgroup
     const int j = __builtin_amdgcn_readfirstlane(bunits[bu].col);
     const int first = __builtin_amdgcn_readfirstlane(bunits[bu].first) + wave * kWave;
+    if (row_unstaged(a, j)) {
+        factor_unstaged<TWONU, COUNT, VT, MASK>(a, j, first, lane);
+        return;
+    }
     if constexpr (MASK) {
         const int np = stage_values(a, j, sval);
         __syncthreads();
@@ -802,6 +826,10 @@ __global__ __launch_bounds__(WPB * kWave) void ichol_persistent(IcholArgs<VT> a,
         for (int64_t bu = ub + slot; bu < ue; bu += stride) {  // the same trip count for the whole workgroup
             const int j = __builtin_amdgcn_readfirstlane(bunits[bu].col);
             const int first = __builtin_amdgcn_readfirstlane(bunits[bu].first) + wave * kWave;
+            if (row_unstaged(a, j)) {
+                factor_unstaged<TWONU, COUNT, VT, MASK>(a, j, first, lane);
+                continue;  // no LDS touched: the workgroup needs no barrier before its next unit
+            }
             if constexpr (MASK) {
                 const int np = stage_values(a, j, sval);
                 __syncthreads();
@@ -1193,6 +1221,50 @@ __global__ __launch_bounds__(kBlock) void bwd_solve(const int32_t* __restrict__ 
     }
 }
 
+// s[r] += sum of L_e * y[row_e][r] over this lane's entries e = e, e + 64, ...
+// below e1, in ascending order: four entries in flight at once, and the row
+// indices of the next four requested before this four's values and gathers,
+// so each step waits for one round trip instead of two.
+template <typename VT, int NR>
+__device__ __forceinline__ void dot_entries(const int32_t* __restrict__ rowidx, const VT* __restrict__ Lcsc, int64_t e,
+                                            int64_t e1, const double* __restrict__ y, int ld, int r0,
+                                            double (&s)[NR]) {
+    constexpr int kDepth = 4;
+    int ci[kDepth];
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) {
+        const int64_t eu = e + int64_t(u) * kWave;
+        ci[u] = eu < e1 ? rowidx[eu] : -1;
+    }
+    for (; e < e1; e += kDepth * kWave) {
+        int cn[kDepth];
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+            const int64_t en = e + int64_t(kDepth + u) * kWave;
+            cn[u] = en < e1 ? rowidx[en] : -1;
+        }
+        double l[kDepth], v[kDepth][NR];
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+            l[u] = 0.0;
+            if (ci[u] >= 0) {
+                l[u] = double(Lcsc[e + int64_t(u) * kWave]);
+                const double* xk = y + int64_t(ci[u]) * ld + r0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) v[u][r] = xk[r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u)
+            if (ci[u] >= 0) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) s[r] = __builtin_fma(l[u], v[u][r], s[r]);
+            }
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) ci[u] = cn[u];
+    }
+}
+
 // Partial dot products of column pieces: one wavefront per piece.
 template <typename VT, int NR>
 __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __restrict__ chunks, int64_t beg,
@@ -1210,28 +1282,7 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] = 0.0;
-    // four entries per lane in flight at once, applied in ascending order
-    constexpr int kDepth = 4;
-    for (int64_t e = e0 + lane; e < e1; e += kDepth * kWave) {
-        double l[kDepth], v[kDepth][NR];
-#pragma unroll
-        for (int u = 0; u < kDepth; ++u) {
-            const int64_t eu = e + int64_t(u) * kWave;
-            l[u] = 0.0;
-            if (eu < e1) {
-                l[u] = double(Lcsc[eu]);
-                const double* xk = y + int64_t(rowidx[eu]) * ld + r0;
-#pragma unroll
-                for (int r = 0; r < NR; ++r) v[u][r] = xk[r];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kDepth; ++u)
-            if (e + int64_t(u) * kWave < e1) {
-#pragma unroll
-                for (int r = 0; r < NR; ++r) s[r] = __builtin_fma(l[u], v[u][r], s[r]);
-            }
-    }
+    dot_entries<VT, NR>(rowidx, Lcsc, e0 + lane, e1, y, ld, r0, s);
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -1275,31 +1326,8 @@ __global__ __launch_bounds__(kBlock) void bwd_finish(const kc::TopCol* __restric
         for (int r = 0; r < NR; ++r) s[r] += pq[r];
     }
     const int64_t c0 = colptr[tc.col];
-    if (tc.n2 == 0) {
-        // rows of the top part: their columns lie in earlier top levels
-        const int64_t e1 = c0 + 1 + tc.ntop;
-        constexpr int kDepth = 4;
-        for (int64_t e = c0 + 1 + lane; e < e1; e += kDepth * kWave) {
-            double l[kDepth], v[kDepth][NR];
-#pragma unroll
-            for (int u = 0; u < kDepth; ++u) {
-                const int64_t eu = e + int64_t(u) * kWave;
-                l[u] = 0.0;
-                if (eu < e1) {
-                    l[u] = double(Lcsc[eu]);
-                    const double* xk = y + int64_t(rowidx[eu]) * ld + r0;
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) v[u][r] = xk[r];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kDepth; ++u)
-                if (e + int64_t(u) * kWave < e1) {
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) s[r] = __builtin_fma(l[u], v[u][r], s[r]);
-                }
-        }
-    }
+    if (tc.n2 == 0)  // rows of the top part: their columns lie in earlier top levels
+        dot_entries<VT, NR>(rowidx, Lcsc, c0 + 1 + lane, c0 + 1 + tc.ntop, y, ld, r0, s);
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -1782,6 +1810,7 @@ IcholArgs<VT> ichol_args(const kc_factor* f, double ell, const double* ells, int
     a.policy = pol;
     a.tau = tau;
     a.cap = f->cap;
+    a.stage_max = f->stage_max;
     a.nbuck = f->nbuck;
     a.counters = f->counters;
     a.mmeta = f->mmeta;
@@ -1905,7 +1934,9 @@ kc_status launch_groups(const kc_factor* f, int tn, double ell, int pol, double 
 }
 
 // Whether a factorization of f runs by supernodal groups (not for update counting).
-bool groups_on(const kc_factor* f, bool count) { return f->use_groups && f->groups && !count && f->prec == KC_MIXED; }
+bool groups_on(const kc_factor* f, bool count) {
+    return f->use_groups && f->groups && !count && f->prec == KC_MIXED && f->max_row <= f->stage_max;
+}
 
 // Forward sweep of levels [l0, l1): y = L^-1 P b for right-hand sides r0 .. r0+NR-1.
 template <typename VT, int NR>
@@ -2307,15 +2338,18 @@ kc_status kc_factor_create(const kc_plan* plan, kc_prec prec, void* ws_dev, size
     const size_t vt = prec == KC_FP64 ? sizeof(double) : sizeof(float);
     f->cap = lds_cap(p);
     f->nbuck = bucket_count(p);
-    if (factor_lds(f.get(), vt) <= kMaxLdsBytes) {
+    f->max_row = p.max_row;
+    if (factor_lds(f.get(), vt) > kMaxLdsBytes) {
+        // rows longer than the LDS holds are read from device memory (row_unstaged)
+        const size_t dir = f->nbuck ? size_t(f->nbuck + 1) * sizeof(uint16_t) : 0;
+        f->cap = int32_t((kMaxLdsBytes - dir - 16) / (vt + sizeof(int32_t)) / 16 * 16);
+    }
+    f->stage_max = f->cap - 2;
+    {
         // a workgroup covers 64 * wpb entries of one column: more wavefronts share one
         // staged row on long columns, fewer leave less padding on short ones
         const double avg = double(p.nnz()) / double(std::max<int64_t>(1, p.n));
         f->wpb = avg >= 1024.0 ? 4 : avg >= 512.0 ? 2 : 1;
-    } else {
-        kc::set_error("kc_factor_create: a row of S is too long to stage in LDS (" + std::to_string(p.max_row) +
-                      " entries)");
-        return KC_ERANGE;
     }
     char* base = static_cast<char*>(ws_dev);
     f->n = p.n;
@@ -2747,7 +2781,7 @@ kc_status kc_factor_match_build(kc_factor* f, void* buf_dev, size_t bytes, void*
         return KC_EWORKSPACE;
     }
     const size_t lds = size_t(kWavesPerBlock) * size_t(f->cap) * sizeof(int32_t);
-    if (lds > kMaxLdsBytes) {
+    if (lds > kMaxLdsBytes || f->max_row > f->stage_max) {
         kc::set_error("kc_factor_match_build: a row of S is too long to stage for the mask build");
         return KC_ERANGE;
     }
@@ -2919,6 +2953,19 @@ kc_status kc_factor_set_schedule(kc_factor* f, int32_t wpb, int64_t persist_max,
     f->wpb = wpb;
     f->persist_max = persist_max;
     f->order = order;
+    return KC_OK;
+}
+
+kc_status kc_factor_set_stage_limit(kc_factor* f, int32_t max_parents) {
+    if (!f || max_parents < -1) {
+        kc::set_error("kc_factor_set_stage_limit: max_parents must be >= -1");
+        return KC_EINVAL;
+    }
+    if (max_parents >= 0 && f->mmeta && f->max_row > max_parents) {
+        kc::set_error("kc_factor_set_stage_limit: match masks are attached and need every row staged");
+        return KC_EINVAL;
+    }
+    f->stage_max = max_parents < 0 ? f->cap - 2 : std::min(max_parents, f->cap - 2);
     return KC_OK;
 }
 

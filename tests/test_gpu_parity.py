@@ -5,10 +5,12 @@ bit-identical (both sides use the correctly rounded exponential), and L is
 bit-identical (same per-entry update order, one fma per update, correctly
 rounded sqrt and division).  Solves are bit-identical whenever every column has
 at most 2048 off-diagonal entries (sequential substitution on both sides).
-Longer columns of the backward sweep are summed in fixed 512-entry pieces,
-which changes the summation order; those solves are held to
+Otherwise the backward sweep sums the columns up to the last long one in fixed
+pieces, which changes the summation order; those solves are held to
 max|x - x_oracle| <= 1e-12 max|x_oracle| for each right-hand side
-(test_long_column_solve_matches_oracle).
+(test_long_column_solve_matches_oracle).  Rows read from device memory instead
+of LDS (kc_factor_set_stage_limit) give the same L bit for bit
+(test_unstaged_rows_give_the_same_factor).
 """
 import numpy as np
 import pytest
@@ -330,3 +332,43 @@ def test_errors_surface_as_exceptions(K):
         f.factorize(dev(w.points[:10]), 1.5, 0.2)
     with pytest.raises(ValueError):
         f.solve(torch.zeros(w.n, dtype=torch.float32, device="cuda"))
+
+
+def test_unstaged_rows_give_the_same_factor(K):
+    """Rows with more parents than the stage limit are read from device memory instead of LDS (the path
+    rows too long for LDS always take): L, pivot counts and U stay bitwise the oracle's in FP64, per level
+    and in persistent launches, and the mixed factor stays bitwise its staged self.  Match masks need
+    every row staged and are refused meanwhile."""
+    print("[gpu] unstaged rows", flush=True)
+    x = W.uniform_points(4000, 2, 31)
+    rho, nu, ell = 14.0, 0.5, 0.2
+    P, th, R = oracle_factor(x, rho, "max", nu, ell)
+    plan = K.analyze(x, rho)
+    assert plan.info()["max_row"] > 200
+    xd = dev(x)
+    f = K.Factor(plan, "fp64")
+    wpb, pm, order = f.schedule()
+    for limit in (0, 40, 200):
+        f.set_stage_limit(limit)
+        for persist in (0, 1 << 40):
+            f.set_schedule(wpb, persist, order)
+            f.factorize(xd, nu, ell, count_updates=True)
+            st = f.stats()
+            assert st.updates == R.updates and st.nonpositive == R.nonpositive, (limit, persist)
+            assert np.array_equal(f.export_L(), R.L), (limit, persist)
+    f.set_schedule(wpb, pm, order)
+    with pytest.raises(RuntimeError):
+        f.build_matches()
+    f.set_stage_limit(-1)
+    f.build_matches()
+    with pytest.raises(RuntimeError):
+        f.set_stage_limit(40)  # masks attached: every row must stay staged
+    f.factorize(xd, nu, ell)
+    assert np.array_equal(f.export_L(), R.L)
+    f.drop_matches()
+    fm = K.Factor(plan, "mixed")
+    fm.factorize(xd, nu, ell, "shift", 1e-6)
+    Lm = fm.export_L()
+    fm.set_stage_limit(40)
+    fm.factorize(xd, nu, ell, "shift", 1e-6)
+    assert np.array_equal(fm.export_L(), Lm)
