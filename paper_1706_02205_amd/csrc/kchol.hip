@@ -1380,7 +1380,7 @@ namespace {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct BwdSchedule {
-    int32_t top = 0;                      // T: one past the last long column (0: none)
+    int32_t top = 0;                      // the largest T (0: no long column in any instance)
     std::vector<int32_t> shortc;          // columns >= T by reverse level
     std::vector<int64_t> short_off;
     std::vector<kc::BwdChunk> chunks;     // the nfine band-major pieces, then the long top parts' pieces
@@ -1390,75 +1390,96 @@ struct BwdSchedule {
     int64_t max_slots = 0;
 };
 
-// The backward sweep's schedule (see the A3 kernels): the columns at or above T
-// by reverse level; the pieces of the top columns' rows at or above T, each
-// within one band of kBandRows row indices, band after band; the top block by
-// its own levels (a column's level is one more than the highest level among the
-// rows of its top part).
+// The backward sweep's schedule (see the A3 kernels), per instance of a batch
+// plan (a single problem is one instance) and merged across instances by level:
+// the columns at or above the instance's T by reverse level; the pieces of its
+// top columns' rows at or above T, each within one band of row indices (bands
+// of at most kBandRows over [T, end of the instance)), band after band; the
+// top block by its own levels (a column's level is one more than the highest
+// level among the rows of its top part).
 BwdSchedule backward_schedule(const kc::Plan& p) {
     BwdSchedule b;
     const int32_t n = p.n;
-    for (int32_t j = 0; j < n; ++j)
-        if (p.colptr[j + 1] - p.colptr[j] - 1 > kLongColumn) b.top = j + 1;
-    const int32_t T = b.top;
+    const int32_t ni = std::max<int32_t>(1, p.ninst);
+    auto inst_begin = [&](int32_t i) -> int32_t { return ni == 1 ? 0 : int32_t(p.inst_off[size_t(i)]); };
+    auto inst_end = [&](int32_t i) -> int32_t { return ni == 1 ? n : int32_t(p.inst_off[size_t(i) + 1]); };
+    // T of each instance: one past its last long column (its first position: no top block)
+    std::vector<int32_t> tops(static_cast<size_t>(ni));
+    for (int32_t i = 0; i < ni; ++i) {
+        int32_t t = inst_begin(i);
+        for (int32_t j = inst_begin(i); j < inst_end(i); ++j)
+            if (p.colptr[j + 1] - p.colptr[j] - 1 > kLongColumn) t = j + 1;
+        tops[size_t(i)] = t;
+        if (t > inst_begin(i)) b.top = std::max(b.top, t);
+    }
+    auto top_of = [&](int32_t j) { return tops[size_t(ni == 1 ? 0 : p.inst[size_t(j)])]; };
     const int32_t nl = p.nrlevels;
     b.short_off.assign(size_t(nl + 1), 0);
     for (int32_t v = 0; v < nl; ++v) {
         for (int64_t q = p.bwd_off[v]; q < p.bwd_off[v + 1]; ++q) {
             const int32_t j = p.bwd_cols[size_t(q)];
-            if (j >= T) b.shortc.push_back(j);
+            if (j >= top_of(j)) b.shortc.push_back(j);
         }
         b.short_off[v + 1] = int64_t(b.shortc.size());
     }
-    if (T == 0) return b;
-    // split of each top column: entries [c0 + 1, fb) have rows < T, [fb, c1) rows >= T
-    std::vector<int64_t> fb(static_cast<size_t>(T));
-    for (int32_t j = 0; j < T; ++j)
-        fb[size_t(j)] = std::lower_bound(p.rowidx.begin() + p.colptr[j] + 1, p.rowidx.begin() + p.colptr[j + 1], T) -
-                        p.rowidx.begin();
-    // pieces of the rows >= T: slots column by column, pieces band after band
-    const int64_t nfine_rows = int64_t(n) - T;
-    const int64_t nb = std::min<int64_t>(64, std::max<int64_t>(1, (nfine_rows + kBandRows - 1) / kBandRows));
-    const int64_t width = (nfine_rows + nb - 1) / nb;
-    std::vector<std::vector<kc::BwdChunk>> band(static_cast<size_t>(nb));
-    std::vector<int32_t> s1(static_cast<size_t>(T)), n1(static_cast<size_t>(T));
+    if (b.top == 0) return b;
+    // top columns: entries [c0 + 1, fb) have rows < T of the instance, [fb, c1) rows >= T
+    std::vector<int64_t> fb(static_cast<size_t>(n), 0);
+    std::vector<int32_t> s1(static_cast<size_t>(n), 0), n1(static_cast<size_t>(n), 0);
     int64_t slot = 0;
-    for (int32_t j = 0; j < T; ++j) {
-        const int64_t c0 = p.colptr[j], c1 = p.colptr[j + 1];
-        s1[size_t(j)] = int32_t(slot);
-        int64_t pos = fb[size_t(j)];
-        for (int64_t q = 0; q < nb && pos < c1; ++q) {
-            const int64_t bound = std::min<int64_t>(int64_t(n), T + (q + 1) * width);
-            const int64_t hi = std::lower_bound(p.rowidx.begin() + pos, p.rowidx.begin() + c1, int32_t(bound)) -
-                               p.rowidx.begin();
-            for (int64_t e = pos; e < hi; e += kFinePiece) {
-                const int64_t len = std::min<int64_t>(kFinePiece, hi - e);
-                band[size_t(q)].push_back(kc::BwdChunk{j, int32_t(e - c0 - 1), int32_t(slot++), int32_t(len)});
+    for (int32_t i = 0; i < ni; ++i) {
+        const int32_t i0 = inst_begin(i), T = tops[size_t(i)], iend = inst_end(i);
+        if (T == i0) continue;
+        for (int32_t j = i0; j < T; ++j)
+            fb[size_t(j)] = std::lower_bound(p.rowidx.begin() + p.colptr[j] + 1, p.rowidx.begin() + p.colptr[j + 1], T) -
+                            p.rowidx.begin();
+        // pieces of the rows >= T: slots column by column, pieces band after band
+        const int64_t nfine_rows = int64_t(iend) - T;
+        const int64_t nb = std::min<int64_t>(64, std::max<int64_t>(1, (nfine_rows + kBandRows - 1) / kBandRows));
+        const int64_t width = std::max<int64_t>(1, (nfine_rows + nb - 1) / nb);
+        std::vector<std::vector<kc::BwdChunk>> band(static_cast<size_t>(nb));
+        for (int32_t j = i0; j < T; ++j) {
+            const int64_t c0 = p.colptr[j], c1 = p.colptr[j + 1];
+            s1[size_t(j)] = int32_t(slot);
+            int64_t pos = fb[size_t(j)];
+            for (int64_t q = 0; q < nb && pos < c1; ++q) {
+                const int64_t bound = std::min<int64_t>(int64_t(iend), T + (q + 1) * width);
+                const int64_t hi = std::lower_bound(p.rowidx.begin() + pos, p.rowidx.begin() + c1, int32_t(bound)) -
+                                   p.rowidx.begin();
+                for (int64_t e = pos; e < hi; e += kFinePiece) {
+                    const int64_t len = std::min<int64_t>(kFinePiece, hi - e);
+                    band[size_t(q)].push_back(kc::BwdChunk{j, int32_t(e - c0 - 1), int32_t(slot++), int32_t(len)});
+                }
+                pos = hi;
             }
-            pos = hi;
+            n1[size_t(j)] = int32_t(slot - s1[size_t(j)]);
         }
-        n1[size_t(j)] = int32_t(slot - s1[size_t(j)]);
+        for (auto& bq : band) b.chunks.insert(b.chunks.end(), bq.begin(), bq.end());
     }
-    for (auto& bq : band) b.chunks.insert(b.chunks.end(), bq.begin(), bq.end());
     b.nfine = int64_t(b.chunks.size());
     const int64_t fine_slots = slot;
     b.max_slots = fine_slots;
-    // levels of the top block
-    std::vector<int32_t> rt(static_cast<size_t>(T), 0);
+    // levels of the top blocks, merged across instances
+    std::vector<int32_t> rt(static_cast<size_t>(n), -1);
     int32_t ntl = 0;
-    for (int32_t j = T - 1; j >= 0; --j) {
-        int32_t m = -1;
-        for (int64_t e = p.colptr[j] + 1; e < fb[size_t(j)]; ++e) m = std::max(m, rt[size_t(p.rowidx[e])]);
-        rt[size_t(j)] = m + 1;
-        ntl = std::max(ntl, m + 2);
+    for (int32_t i = 0; i < ni; ++i) {
+        const int32_t i0 = inst_begin(i), T = tops[size_t(i)];
+        for (int32_t j = T - 1; j >= i0; --j) {
+            int32_t m = -1;
+            for (int64_t e = p.colptr[j] + 1; e < fb[size_t(j)]; ++e) m = std::max(m, rt[size_t(p.rowidx[e])]);
+            rt[size_t(j)] = m + 1;
+            ntl = std::max(ntl, m + 2);
+        }
     }
     std::vector<int64_t> cnt(size_t(ntl) + 1, 0);
-    for (int32_t j = 0; j < T; ++j) ++cnt[size_t(rt[size_t(j)]) + 1];
+    for (int32_t j = 0; j < n; ++j)
+        if (rt[size_t(j)] >= 0) ++cnt[size_t(rt[size_t(j)]) + 1];
     for (int32_t v = 0; v < ntl; ++v) cnt[size_t(v) + 1] += cnt[size_t(v)];
-    std::vector<int32_t> bylevel(static_cast<size_t>(T));
+    std::vector<int32_t> bylevel(static_cast<size_t>(cnt[size_t(ntl)]));
     {
         std::vector<int64_t> at(cnt.begin(), cnt.end() - 1);
-        for (int32_t j = 0; j < T; ++j) bylevel[size_t(at[size_t(rt[size_t(j)])]++)] = j;
+        for (int32_t j = 0; j < n; ++j)
+            if (rt[size_t(j)] >= 0) bylevel[size_t(at[size_t(rt[size_t(j)])]++)] = j;
     }
     b.top_off.assign(size_t(ntl) + 1, 0);
     b.tchunk_off.assign(size_t(ntl) + 1, 0);

@@ -201,3 +201,28 @@ def test_batched_mixed_error(K, batch):
         e0 += P.nnz
     print(f"[gpu] batched mixed: worst ||dL||/||L|| over instances without zeroed columns {worst:.2e}", flush=True)
     assert worst < 1e-3
+
+
+def test_batch_with_long_columns_solves_each_instance_as_alone(K):
+    """Instances with columns longer than 2048 entries: each instance gets its own top block (its last long
+    column bounds it), and the stages are merged across instances by level -- so every instance's solution
+    is bitwise the one it gets when solved alone, and within 1e-12 max|x| of the oracle's sequential solve."""
+    print("[gpu] batched long columns", flush=True)
+    xs = [W.uniform_points(5000, 2, 4301), W.uniform_points(1200, 2, 4302), W.uniform_points(3000, 2, 4303)]
+    ells = np.array([0.2, 0.3, 0.25])
+    b = np.concatenate([W.gaussian_rhs(len(x), 3, 4400 + i) for i, x in enumerate(xs)])
+    plan, f, xd, ed = run_batch(K, xs, ells)
+    sol = f.solve(dev(b)).cpu().numpy()
+    o0 = 0
+    for i, (x, ell) in enumerate(zip(xs, ells)):
+        bi = b[o0:o0 + len(x)]
+        alone = K.Factor(K.analyze(x, 3.0), "fp64")
+        alone.factorize(dev(x), 1.5, float(ell))
+        xa = alone.solve(dev(bi)).cpu().numpy()
+        assert np.array_equal(sol[o0:o0 + len(x)], xa), f"instance {i}"
+        P = O.pattern(x, 3.0)
+        R = O.ichol(P, O.theta_on_pattern(P, 1.5, float(ell)))
+        xr = O.solve(P, R.L, bi)
+        err = np.abs(xa - xr).max(axis=0) / np.abs(xr).max(axis=0)
+        assert np.all(err <= 1e-12), (i, err)
+        o0 += len(x)
