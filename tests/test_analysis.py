@@ -126,3 +126,15 @@ def test_supernodal_plan_matches_oracle(n, d, rho, seed):
     np.testing.assert_array_equal(cp, Pn.colptr)
     np.testing.assert_array_equal(ri, Pn.rowidx)
     np.testing.assert_array_equal(p.supernodes(), sptr)
+
+
+def test_supernodal_plan_of_a_worked_example():
+    """The host's supernodal ordering on the hand-worked example (tests/golden/supernodes_line9.json)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "supernodes_line9.json")) as f:
+        g = json.load(f)
+    x = np.array(g["points"], dtype=np.float64).reshape(-1, 1)
+    p = K.analyze_supernodal(x, g["rho"])
+    np.testing.assert_array_equal(p.export()[0], g["supernodal_perm"])
+    np.testing.assert_array_equal(p.supernodes(), g["supernode_ptr"])

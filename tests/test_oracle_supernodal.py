@@ -59,3 +59,19 @@ def test_supernodal_pattern_is_at_least_as_accurate():
     Pn, _ = O.supernodal_pattern(x, 2.0)
     e_super = O.frob_error(Pn, O.ichol(Pn, O.theta_on_pattern(Pn, 0.5, 0.2)).L, 0.5, 0.2)
     assert e_super <= e_plain
+
+
+def test_supernodes_of_a_worked_example():
+    """Nine points on a line, rho = 2: the ordering and supernodes worked out by hand from the paper's
+    construction (tests/golden/supernodes_line9.json holds the derivation)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "supernodes_line9.json")) as f:
+        g = json.load(f)
+    x = np.array(g["points"], dtype=np.float64).reshape(-1, 1)
+    P = O.pattern(x, g["rho"])
+    np.testing.assert_array_equal(P.perm, g["maximin_perm"])
+    np.testing.assert_array_equal(P.l, [float(v) for v in g["maximin_l"]])
+    Pn, sptr = O.supernodal_pattern(x, g["rho"])
+    np.testing.assert_array_equal(Pn.perm, g["supernodal_perm"])
+    np.testing.assert_array_equal(sptr, g["supernode_ptr"])
