@@ -232,9 +232,10 @@ def assert_close_per_rhs(x, ref, what):
 
 @pytest.mark.parametrize("nrhs", [1, 8, 11])
 def test_long_column_solve_matches_oracle(K, nrhs):
-    """Columns with more than 2048 off-diagonal entries take the piecewise backward path
-    (fixed 512-entry pieces, then a fixed-order combine): compared with the oracle's
-    sequential substitution element by element, for kc_solve and kc_factorize_solve."""
+    """Columns with more than 2048 off-diagonal entries: the backward sweep runs its three stages
+    (columns past the last long one by reverse level, the top columns' rows below the top block in
+    banded pieces, the top block by its own levels, sums in a fixed order): compared with the
+    oracle's sequential substitution element by element, for kc_solve and kc_factorize_solve."""
     print(f"[gpu] long-column solve parity nrhs={nrhs}", flush=True)
     x = W.uniform_points(5000, 2, 33)
     P, th, R = oracle_factor(x, 3.0, "max", 1.5, 0.2)
