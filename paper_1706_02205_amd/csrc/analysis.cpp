@@ -7,7 +7,7 @@
 // tree search around the newly selected point instead of parent/child lists:
 // a subtree is entered only if its box may hold an unselected point closer than
 // that point's current distance (per-node upper bounds of those distances).
-// From kParallelOrderMin points on, the ordering takes batches of heap
+// With enough points and threads, the ordering takes batches of heap
 // candidates at once and applies their updates on several threads; the output
 // is the same (see maximin_parallel).  Every comparison that decides the output uses the same
 // floating-point expression as the definition, so the result is exactly the
@@ -286,7 +286,7 @@ struct MaxHeap {
 // Reusable barrier for a fixed team of threads: spins briefly, then sleeps, so
 // that teams of concurrent analyses (a server's) do not burn each other's cores.
 class TeamBarrier {
-    static constexpr int kSpins = 1 << 15;  // about 0.1-0.3 ms of pauses: longer than a batch phase
+    static constexpr int kSpins = 1 << 10;
 
 public:
     explicit TeamBarrier(int n) : n_(n) {}
@@ -317,11 +317,15 @@ private:
     std::condition_variable cv_;
 };
 
-// Below this size the ordering runs on one thread; above, on at most
-// kOrderThreads (a batch waits for its slowest thread four times, so more
-// threads gain little and lose much when other work shares the cores).
+// The ordering runs in batches on several threads (at most kOrderThreads)
+// only from kParallelOrderMin points and when the analysis is given at least
+// kOrderThreadsMin threads: the batches add work (conflict checks, merging the
+// heaps' candidates) that shortens one analysis but costs throughput when
+// concurrent analyses share the cores, and a batch waits for its slowest
+// thread four times, so more threads gain little.
 constexpr int64_t kParallelOrderMin = 16384;
 constexpr int kOrderThreads = 4;
+constexpr int kOrderThreadsMin = 8;
 
 // The exact greedy maximin ordering on several threads: the same output as the
 // one-thread loop in maximin_order, by this argument.  Candidates leave the
@@ -467,7 +471,7 @@ void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t*
     for (int64_t t = 0; t < n; ++t)
         std::copy(x + size_t(tree.idx[t]) * d, x + size_t(tree.idx[t] + 1) * d, xt.begin() + size_t(t) * d);
     nthreads = resolve_threads(nthreads);
-    if (nthreads > 1 && n >= kParallelOrderMin) {
+    if (nthreads >= kOrderThreadsMin && n >= kParallelOrderMin) {
         maximin_parallel(tree, xt, n, d, std::min(nthreads, kOrderThreads), perm, l);
         return;
     }

@@ -80,14 +80,17 @@ class ServeStats:
 class Server:
     def __init__(self, nu: float, lengthscale: float, rho: float, prec: str = "mixed", budget_bytes: float = 64e9,
                  max_inflight: int = 8, nstreams: int = 4, analysis_threads: int = 8,
-                 analysis_nthreads: Optional[int] = None, max_bypass: int = 8):
+                 analysis_nthreads: Optional[int] = None, max_bypass: int = 8,
+                 max_analysis_threads: int = 8, points_per_thread: int = 25_000):
         import torch
         self.nu, self.ell, self.rho, self.prec = nu, lengthscale, rho, prec
         self.pivot, self.tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
         self.budget = int(budget_bytes)
-        # host threads inside one request's analysis; None: by size, one per 25,000 points (1 to 8), so
-        # that the largest requests -- the latency tail -- get the most threads
+        # host threads inside one request's analysis; None: by size, one per points_per_thread points (1 to
+        # max_analysis_threads), so that the largest requests -- the latency tail -- get the most threads
         self.analysis_nthreads = analysis_nthreads
+        self.max_analysis_threads = max_analysis_threads
+        self.points_per_thread = points_per_thread
         self.max_inflight = max_inflight
         self.max_bypass = max_bypass
         self._bypassed = 0      # times the current head of the ready queue has been passed
@@ -109,7 +112,7 @@ class Server:
         res = RequestResult(rid, len(points), 0, arrival if arrival is not None else time.perf_counter())
         self.results[rid] = res
 
-        nth = self.analysis_nthreads or max(1, min(8, len(points) // 25_000))
+        nth = self.analysis_nthreads or max(1, min(self.max_analysis_threads, len(points) // self.points_per_thread))
 
         def work():
             plan = analyze(points, self.rho, nthreads=nth)
