@@ -81,7 +81,7 @@ class Server:
     def __init__(self, nu: float, lengthscale: float, rho: float, prec: str = "mixed", budget_bytes: float = 64e9,
                  max_inflight: int = 8, nstreams: int = 4, analysis_threads: int = 8,
                  analysis_nthreads: Optional[int] = None, max_bypass: int = 8,
-                 max_analysis_threads: int = 8, points_per_thread: int = 25_000):
+                 max_analysis_threads: int = 16, points_per_thread: int = 12_500):
         import torch
         self.nu, self.ell, self.rho, self.prec = nu, lengthscale, rho, prec
         self.pivot, self.tau = ("zero", 0.0) if prec == "fp64" else ("shift", 1e-6)
