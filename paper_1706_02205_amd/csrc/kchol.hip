@@ -1221,11 +1221,11 @@ __global__ __launch_bounds__(kBlock) void bwd_solve(const int32_t* __restrict__ 
     }
 }
 
-// s[r] += sum of L_e * y[row_e][r] over this lane's entries e = e, e + 64, ...
-// below e1, in ascending order: four entries in flight at once, and the row
+// s[r] += sum of L_e * y[row_e][r] over this lane's entries e = e, e + STRIDE,
+// ... below e1, in ascending order: four entries in flight at once, and the row
 // indices of the next four requested before this four's values and gathers,
 // so each step waits for one round trip instead of two.
-template <typename VT, int NR>
+template <typename VT, int NR, int STRIDE = kWave>
 __device__ __forceinline__ void dot_entries(const int32_t* __restrict__ rowidx, const VT* __restrict__ Lcsc, int64_t e,
                                             int64_t e1, const double* __restrict__ y, int ld, int r0,
                                             double (&s)[NR]) {
@@ -1233,14 +1233,14 @@ __device__ __forceinline__ void dot_entries(const int32_t* __restrict__ rowidx, 
     int ci[kDepth];
 #pragma unroll
     for (int u = 0; u < kDepth; ++u) {
-        const int64_t eu = e + int64_t(u) * kWave;
+        const int64_t eu = e + int64_t(u) * STRIDE;
         ci[u] = eu < e1 ? rowidx[eu] : -1;
     }
-    for (; e < e1; e += kDepth * kWave) {
+    for (; e < e1; e += kDepth * STRIDE) {
         int cn[kDepth];
 #pragma unroll
         for (int u = 0; u < kDepth; ++u) {
-            const int64_t en = e + int64_t(kDepth + u) * kWave;
+            const int64_t en = e + int64_t(kDepth + u) * STRIDE;
             cn[u] = en < e1 ? rowidx[en] : -1;
         }
         double l[kDepth], v[kDepth][NR];
@@ -1248,7 +1248,7 @@ __device__ __forceinline__ void dot_entries(const int32_t* __restrict__ rowidx, 
         for (int u = 0; u < kDepth; ++u) {
             l[u] = 0.0;
             if (ci[u] >= 0) {
-                l[u] = double(Lcsc[e + int64_t(u) * kWave]);
+                l[u] = double(Lcsc[e + int64_t(u) * STRIDE]);
                 const double* xk = y + int64_t(ci[u]) * ld + r0;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) v[u][r] = xk[r];
@@ -1296,9 +1296,11 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     }
 }
 
-// Completes the top columns of one top level: a wavefront per column; its lanes
-// add the column's piece sums (lanes take every 64th) and, for a short top part,
-// its entries (every 64th, four in flight), then a fixed butterfly.
+// Completes the top columns of one top level: a workgroup per column.  Its
+// threads add the column's piece sums (thread t takes every kBlock-th slot)
+// and, for a short top part, its entries (every kBlock-th, four in flight);
+// each wavefront reduces by a fixed butterfly, and the four wavefront sums are
+// added in wavefront order; x_j = (y_j - sum) / L_jj.
 template <typename VT, int NR>
 __global__ __launch_bounds__(kBlock) void bwd_finish(const kc::TopCol* __restrict__ tcols, int64_t beg, int64_t end,
                                                      const int64_t* __restrict__ colptr,
@@ -1307,27 +1309,29 @@ __global__ __launch_bounds__(kBlock) void bwd_finish(const kc::TopCol* __restric
                                                      const int32_t* __restrict__ perm, int ld, int r0,
                                                      const double* __restrict__ partial, double* __restrict__ y,
                                                      double* __restrict__ x) {
+    __shared__ double wsum[kWavesPerBlock][NR];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
-    if (t >= end) return;
+    const int64_t t = beg + int64_t(xcd_block());
+    if (t >= end) return;  // the whole workgroup
     const kc::TopCol tc = tcols[t];
+    const int tid = int(threadIdx.x);
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] = 0.0;
-    for (int q = lane; q < tc.n1; q += kWave) {
+    for (int q = tid; q < tc.n1; q += kBlock) {
         const double* pq = partial + int64_t(tc.s1 + q) * NR;
 #pragma unroll
         for (int r = 0; r < NR; ++r) s[r] += pq[r];
     }
-    for (int q = lane; q < tc.n2; q += kWave) {
+    for (int q = tid; q < tc.n2; q += kBlock) {
         const double* pq = partial + int64_t(tc.s2 + q) * NR;
 #pragma unroll
         for (int r = 0; r < NR; ++r) s[r] += pq[r];
     }
     const int64_t c0 = colptr[tc.col];
     if (tc.n2 == 0)  // rows of the top part: their columns lie in earlier top levels
-        dot_entries<VT, NR>(rowidx, Lcsc, c0 + 1 + lane, c0 + 1 + tc.ntop, y, ld, r0, s);
+        dot_entries<VT, NR, kBlock>(rowidx, Lcsc, c0 + 1 + tid, c0 + 1 + tc.ntop, y, ld, r0, s);
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -1337,6 +1341,13 @@ __global__ __launch_bounds__(kBlock) void bwd_finish(const kc::TopCol* __restric
 #pragma unroll
         for (int r = 1; r < NR; ++r)
             if (lane == r) v = s[r];
+        wsum[wave][lane] = v;
+    }
+    __syncthreads();
+    if (wave == 0 && lane < NR) {
+        double v = wsum[0][lane];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) v += wsum[w][lane];
         const double ljj = diag_value(Lcsc, diag, c0, tc.col);
         double* yj = y + int64_t(tc.col) * ld + r0 + lane;
         const double xv = (ljj == 0.0) ? 0.0 : (*yj - v) / ljj;
@@ -2003,7 +2014,7 @@ kc_status bwd_levels(const kc_factor* f, double* x, int ld, int r0, double* y, d
         }
         const int64_t tb = f->top_off[v], te = f->top_off[v + 1];
         if (te > tb) {
-            bwd_finish<VT, NR><<<grid_for(te - tb, kWavesPerBlock), kBlock, 0, s>>>(
+            bwd_finish<VT, NR><<<unsigned(te - tb), kBlock, 0, s>>>(
                 f->bwd_top, tb, te, f->colptr, f->rowidx, Lc, f->diag, f->perm, ld, r0, partial, y, x);
             KC_LAUNCH_CHECK();
         }
