@@ -1296,6 +1296,53 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     }
 }
 
+// Forward levels with at least kWideRows rows are throughput-bound: there a
+// wavefront's 64 lanes share a row's dot product (every 64th entry, four in
+// flight) and a fixed butterfly adds them, instead of 8 lanes applying staged
+// chunks in the sequential order.  Deterministic, but not the sequential
+// substitution's summation order; smaller levels keep that order.
+constexpr int64_t kWideRows = 4096;
+
+template <typename VT, int NR>
+__device__ __forceinline__ double wave_dot(const int32_t* __restrict__ idx, const VT* __restrict__ val, int64_t b0,
+                                           int64_t b1, const double* __restrict__ src, int ld, int r0, int lane) {
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[r] = 0.0;
+    dot_entries<VT, NR>(idx, val, b0 + lane, b1, src, ld, r0, s);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s[r] += __shfl_xor(s[r], off, kWave);
+    double v = s[0];
+#pragma unroll
+    for (int r = 1; r < NR; ++r)
+        if (lane == r) v = s[r];
+    return v;  // lane r < NR holds right-hand side r's sum
+}
+
+template <typename VT, int NR>
+__global__ __launch_bounds__(kBlock) void fwd_wide(const int32_t* __restrict__ rows, int64_t beg, int64_t end,
+                                                   const int64_t* __restrict__ rowptr,
+                                                   const int64_t* __restrict__ rowend,
+                                                   const int32_t* __restrict__ colidx, const VT* __restrict__ Lv,
+                                                   const double* __restrict__ diag, const int32_t* __restrict__ perm,
+                                                   const double* __restrict__ b, int ld, int r0,
+                                                   double* __restrict__ y) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t t = beg + int64_t(xcd_block()) * kWavesPerBlock + wave;
+    if (t >= end) return;
+    const int k = __builtin_amdgcn_readfirstlane(rows[t]);
+    const int64_t p0 = rowptr[k], pd = rowend[k] - 1;  // pd: the diagonal
+    const double v = wave_dot<VT, NR>(colidx, Lv, p0, pd, y, ld, r0, lane);
+    if (lane < NR) {
+        const double lkk = diag_value(Lv, diag, pd, k);
+        const double acc = b[int64_t(perm[k]) * ld + r0 + lane] - v;
+        y[int64_t(k) * ld + r0 + lane] = (lkk == 0.0) ? 0.0 : acc / lkk;
+    }
+}
+
 // Completes the top columns of one top level: a workgroup per column.  Its
 // threads add the column's piece sums (thread t takes every kBlock-th slot)
 // and, for a short top part, its entries (every kBlock-th, four in flight);
@@ -1978,8 +2025,12 @@ kc_status fwd_levels(const kc_factor* f, const double* b, int ld, int r0, double
     for (size_t v = l0; v < l1; ++v) {
         const int64_t rb = f->fwd_off[v], re = f->fwd_off[v + 1];
         if (re <= rb) continue;
-        fwd_solve<VT, NR><<<grid_for(re - rb, kWavesPerBlock), kBlock, 0, s>>>(
-            f->fwd_rows, rb, re, f->rowptr, f->rowend, f->colidx, Lv, f->diag, f->perm, b, ld, r0, y);
+        if (re - rb >= kWideRows)
+            fwd_wide<VT, NR><<<grid_for(re - rb, kWavesPerBlock), kBlock, 0, s>>>(
+                f->fwd_rows, rb, re, f->rowptr, f->rowend, f->colidx, Lv, f->diag, f->perm, b, ld, r0, y);
+        else
+            fwd_solve<VT, NR><<<grid_for(re - rb, kWavesPerBlock), kBlock, 0, s>>>(
+                f->fwd_rows, rb, re, f->rowptr, f->rowend, f->colidx, Lv, f->diag, f->perm, b, ld, r0, y);
         KC_LAUNCH_CHECK();
     }
     return KC_OK;

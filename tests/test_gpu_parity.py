@@ -4,9 +4,11 @@ FP64 bar: the pattern is bit-identical (host analysis), Theta on S is
 bit-identical (both sides use the correctly rounded exponential), and L is
 bit-identical (same per-entry update order, one fma per update, correctly
 rounded sqrt and division).  Solves are bit-identical whenever every column has
-at most 2048 off-diagonal entries (sequential substitution on both sides).
-Otherwise the backward sweep sums the columns up to the last long one in fixed
-pieces, which changes the summation order; those solves are held to
+at most 2048 off-diagonal entries and every forward level fewer than 4096 rows
+(sequential substitution on both sides; the workloads here have at most a few
+hundred rows per level).  Otherwise the backward sweep sums the columns up to
+the last long one in fixed pieces (and large forward levels sum a row across a
+wavefront), which changes the summation order; those solves are held to
 max|x - x_oracle| <= 1e-12 max|x_oracle| for each right-hand side
 (test_long_column_solve_matches_oracle).  Rows read from device memory instead
 of LDS (kc_factor_set_stage_limit) give the same L bit for bit
