@@ -11,8 +11,9 @@ at 10^6 points.  Checked against the oracle in full, not on samples:
 * L in FP64: bitwise, under both orders of the units within a level (LONGEST is
   built on request here, since no level of this size exceeds the device);
 * kc_solve and kc_factorize_solve: max|x - x_oracle| <= 1e-12 max|x_oracle| per
-  right-hand side (the long columns are summed in fixed pieces, not in the
-  oracle's sequential order), the fused call bitwise equal to the separate one;
+  right-hand side (the long columns are summed in fixed pieces and the large
+  forward levels across a wavefront, not in the oracle's sequential order), the
+  fused call bitwise equal to the separate one;
 * the mixed factor (FP32 updates, FP64 pivots) has no bitwise bar: its error
   against the FP64 oracle is stated (per-column maximum and Frobenius).
 """
