@@ -195,7 +195,7 @@ kc_status kc_solve_bytes(const kc_factor *f, int32_t nrhs, size_t *bytes);
 /* x = P^T L^{-T} L^{-1} P b (Section 1, task (2)).  b_dev, x_dev: N x nrhs
  * row-major float64 in original order (may not alias).  A zeroed column gives
  * solution component 0.  Requires a completed kc_factorize on the same factor.
- * Forward levels of fewer than 4096 rows and the backward sweep over short
+ * Forward levels of fewer than 1024 rows and the backward sweep over short
  * columns follow the sequential substitution (bitwise); larger forward levels
  * sum each row across a wavefront, and when a column has more than 2048
  * off-diagonal entries, the columns up to the last such one are summed in

@@ -1296,12 +1296,13 @@ __global__ __launch_bounds__(kBlock) void bwd_partial(const kc::BwdChunk* __rest
     }
 }
 
-// Forward levels with at least kWideRows rows are throughput-bound: there a
-// wavefront's 64 lanes share a row's dot product (every 64th entry, four in
-// flight) and a fixed butterfly adds them, instead of 8 lanes applying staged
-// chunks in the sequential order.  Deterministic, but not the sequential
-// substitution's summation order; smaller levels keep that order.
-constexpr int64_t kWideRows = 4096;
+// Forward levels of at least kWideRows rows: there a wavefront's 64 lanes share
+// a row's dot product (every 64th entry, four in flight) and a fixed butterfly
+// adds them, instead of 8 lanes applying staged chunks in the sequential
+// order -- more throughput on large levels and a shorter chain per row on
+// medium ones.  Deterministic, but not the sequential substitution's
+// summation order; smaller levels keep that order.
+constexpr int64_t kWideRows = 1024;
 
 template <typename VT, int NR>
 __device__ __forceinline__ double wave_dot(const int32_t* __restrict__ idx, const VT* __restrict__ val, int64_t b0,

@@ -4,7 +4,7 @@ FP64 bar: the pattern is bit-identical (host analysis), Theta on S is
 bit-identical (both sides use the correctly rounded exponential), and L is
 bit-identical (same per-entry update order, one fma per update, correctly
 rounded sqrt and division).  Solves are bit-identical whenever every column has
-at most 2048 off-diagonal entries and every forward level fewer than 4096 rows
+at most 2048 off-diagonal entries and every forward level fewer than 1024 rows
 (sequential substitution on both sides; the workloads here have at most a few
 hundred rows per level).  Otherwise the backward sweep sums the columns up to
 the last long one in fixed pieces (and large forward levels sum a row across a
