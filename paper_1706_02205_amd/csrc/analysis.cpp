@@ -89,23 +89,40 @@ struct KDTree {
 
     static constexpr int kLeaf = 16;
 
-    void build(const double* p, int64_t n, int dim) {
+    // Nodes of a subtree in pre-order (ids local to it) with their boxes.
+    struct Sub {
+        std::vector<Node> nodes;
+        std::vector<double> lo, hi;
+    };
+
+    // From kParallelBuild points on, the two halves of the top levels are built
+    // on separate threads (each works on its own range of idx) and appended in
+    // pre-order, so the tree is the one the one-thread build gives.
+    static constexpr int64_t kParallelBuild = 65536;
+
+    void build(const double* p, int64_t n, int dim, int nthreads = 1) {
         pts = p;
         d = dim;
         idx.resize(n);
         for (int64_t i = 0; i < n; ++i) idx[i] = int32_t(i);
-        nodes.clear();
-        nodes.reserve(size_t(2 * (n / kLeaf + 1)));
-        build_node(0, int32_t(n));
+        int par_depth = 0;
+        if (n >= kParallelBuild)
+            while ((1 << par_depth) < nthreads && par_depth < 4) ++par_depth;
+        Sub root;
+        root.nodes.reserve(size_t(2 * (n / kLeaf + 1)));
+        build_node(0, int32_t(n), 0, par_depth, root);
+        nodes = std::move(root.nodes);
+        lo = std::move(root.lo);
+        hi = std::move(root.hi);
     }
 
-    int32_t build_node(int32_t b, int32_t e) {
-        int32_t id = int32_t(nodes.size());
-        nodes.push_back(Node{b, e, -1, -1, 0, 0});
-        lo.resize(size_t(nodes.size()) * d);
-        hi.resize(size_t(nodes.size()) * d);
-        double* L = &lo[size_t(id) * d];
-        double* H = &hi[size_t(id) * d];
+    int32_t build_node(int32_t b, int32_t e, int depth, int par_depth, Sub& s) {
+        int32_t id = int32_t(s.nodes.size());
+        s.nodes.push_back(Node{b, e, -1, -1, 0, 0});
+        s.lo.resize(size_t(s.nodes.size()) * d);
+        s.hi.resize(size_t(s.nodes.size()) * d);
+        double* L = &s.lo[size_t(id) * d];
+        double* H = &s.hi[size_t(id) * d];
         for (int t = 0; t < d; ++t) {
             L[t] = std::numeric_limits<double>::infinity();
             H[t] = -std::numeric_limits<double>::infinity();
@@ -120,8 +137,8 @@ struct KDTree {
             mn = std::min(mn, idx[i]);
             mx = std::max(mx, idx[i]);
         }
-        nodes[id].minid = mn;
-        nodes[id].maxid = mx;
+        s.nodes[id].minid = mn;
+        s.nodes[id].maxid = mx;
         if (e - b <= kLeaf) return id;
         int ax = 0;
         double w = -1.0;
@@ -136,10 +153,29 @@ struct KDTree {
             double a = pts[size_t(u) * d + ax], c = pts[size_t(v) * d + ax];
             return a < c || (a == c && u < v);
         });
-        int32_t l = build_node(b, mid);
-        int32_t r = build_node(mid, e);
-        nodes[id].left = l;
-        nodes[id].right = r;
+        if (depth < par_depth) {
+            Sub right;
+            std::thread th([&] { build_node(mid, e, depth + 1, par_depth, right); });
+            const int32_t l = build_node(b, mid, depth + 1, par_depth, s);
+            th.join();
+            const int32_t off = int32_t(s.nodes.size());
+            for (Node nd : right.nodes) {
+                if (nd.left >= 0) {
+                    nd.left += off;
+                    nd.right += off;
+                }
+                s.nodes.push_back(nd);
+            }
+            s.lo.insert(s.lo.end(), right.lo.begin(), right.lo.end());
+            s.hi.insert(s.hi.end(), right.hi.begin(), right.hi.end());
+            s.nodes[id].left = l;
+            s.nodes[id].right = off;
+        } else {
+            const int32_t l = build_node(b, mid, depth + 1, par_depth, s);
+            const int32_t r = build_node(mid, e, depth + 1, par_depth, s);
+            s.nodes[id].left = l;
+            s.nodes[id].right = r;
+        }
         return id;
     }
 
@@ -464,7 +500,7 @@ void maximin_parallel(const KDTree& tree, const std::vector<double>& xt, int64_t
 
 void maximin_order(const double* x, int64_t n, int32_t d, int nthreads, int32_t* perm, double* l) {
     KDTree tree;
-    tree.build(x, n, d);
+    tree.build(x, n, d, resolve_threads(nthreads));
     // The working arrays are laid out in tree order (slot t holds point tree.idx[t]),
     // so that scanning a leaf reads contiguous memory.
     std::vector<double> xt(size_t(n) * d);
@@ -671,7 +707,7 @@ void build_pattern(Plan& p, int nthreads) {
     const int d = p.d;
     const double* xh = p.xh.data();
     KDTree tree;
-    tree.build(xh, n, d);
+    tree.build(xh, n, d, nthreads);
     p.spatial = tree.idx;  // k-d tree leaf order: positions grouped by region
     // points copied into tree order, so that scanning a leaf reads contiguous memory
     const std::vector<int32_t>& idt = tree.idx;
